@@ -1,0 +1,174 @@
+/*
+ * ucac.h -- C-ABI of the MI355X (gfx950) library that runs the inner iteration of
+ * the two-level component-based ADMM for unit commitment with AC optimal power
+ * flow (UC-ACOPF) of Zhang, Kim & Kim, "On Solving Unit Commitment with
+ * Alternating Current Optimal Power Flow on GPU".
+ *
+ * One inner iteration (Sec. III-A, steps step:uc .. step:y, in that order) is:
+ *   1. one dynamic program per generator for the commitments (Sec. III-B,
+ *      Alg. dp_algo);
+ *   2. one closed-form update per (generator, period) and one trust-region
+ *      Newton solve per (line, period) for the ACOPF variables (step:opf);
+ *   3. the relaxed commitment duplicates in [0,1] (step:uc_bar) and one
+ *      balance-constrained projection per (bus, period) (step:opf_bar),
+ *      a Jacobi pair (both read the other's previous value);
+ *   4. the artificial variable z and the multiplier y of every coupling row
+ *      (step:z, step:y), the residuals, and the outer update of lambda and
+ *      beta (step:outer, tau = 6, theta = 0.8) when the inner loop ends.
+ *
+ * Every function returns UCAC_OK (0) or a status below.  A negative status
+ * leaves the handle's iterate as it was before the call.  All pointers to
+ * arrays are HOST pointers unless stated; the library copies what it needs and
+ * never keeps a caller pointer.  A handle is not thread-safe; different handles
+ * are independent.  Floating point is IEEE FP64 throughout.
+ */
+#ifndef UCAC_H
+#define UCAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  UCAC_OK = 0,
+  UCAC_NOT_CONVERGED = 1,  /* ucac_solve hit max_iters before the tolerance */
+  UCAC_E_INVAL = -1,       /* bad argument or network data (see ucac_last_error) */
+  UCAC_E_NOMEM = -2,       /* device or host allocation failed */
+  UCAC_E_DEVICE = -3,      /* a HIP runtime call failed */
+  UCAC_E_STATE = -4,       /* state buffer of the wrong size or content */
+  UCAC_E_NUMERIC = -5      /* a NaN/Inf appeared in the iterate */
+};
+
+typedef struct ucac_handle ucac_handle;
+
+/* Network and unit data of one instance (Sec. II: eq:uc-acopf, eq:acopf, set:UC,
+ * eq:coupling).  Per-unit quantities on base_mva.  Arrays indexed [t][k] are
+ * row-major with T rows.  All indices are 0-based.  Read only during create. */
+typedef struct {
+  int32_t n_bus, n_line, n_gen, T, ref_bus;
+  double base_mva;
+  const int32_t *line_from, *line_to;        /* [n_line] end buses, from != to */
+  const double *line_r, *line_x, *line_b;    /* [n_line] series r, x and total charging b (pi model) */
+  const double *line_rate;                   /* [n_line] MVA limit r-bar at both ends (uc_acopf_ij/ji_limit) */
+  const double *bus_gs, *bus_bs;             /* [n_bus] shunt G^s, B^s (balance equations) */
+  const double *bus_vmin, *bus_vmax;         /* [n_bus] voltage magnitude bounds (uc_acopf_w_bound) */
+  const double *load_p, *load_q;             /* [T][n_bus] demand P_{t,i}, Q_{t,i} */
+  const int32_t *gen_bus;                    /* [n_gen] */
+  const double *gen_pmin, *gen_pmax;         /* P-lo, P-bar of eq:coupling; ACOPF box is [0, P-bar] */
+  const double *gen_qmin, *gen_qmax;         /* Q-lo, Q-bar; ACOPF box is [min(0,Q-lo), max(0,Q-bar)] */
+  const double *gen_c2, *gen_c1;             /* generation cost c2 p^2 + c1 p in $/MW^2h, $/MWh */
+  const double *gen_cnl, *gen_csu, *gen_csd; /* no-load ($/h), start-up ($), shut-down ($) costs */
+  const double *gen_ru, *gen_rd;             /* ramp-up / ramp-down limits R^U, R^D (p.u. per period) */
+  const double *gen_su, *gen_sd;             /* start-up / shut-down ramps S^U, S^D */
+  const int32_t *gen_min_up, *gen_min_dn;    /* T^U, T^D >= 1 (uc_minup, uc_mindn) */
+  const int32_t *gen_u0;                     /* u^on_{0,g} in {0,1} */
+  const int32_t *gen_init_on, *gen_init_off; /* L_g, F_g (uc_initial_on/off) */
+  const double *gen_p0;                      /* p_{0,g} */
+} ucac_network;
+
+/* Algorithm parameters.  ucac_params_default fills the defaults in brackets. */
+typedef struct {
+  double rho_pq;      /* [5e3] penalty of power rows (line flows, generator p, q) */
+  double rho_va;      /* [1e4] penalty of voltage-square and angle rows */
+  double rho_uc;      /* [1e5] penalty of commitment duplicate rows */
+  double rho_cpl;     /* [5e3] penalty of the six bound/ramp coupling rows */
+  double beta0;       /* [1e5] initial outer penalty beta */
+  double tau, theta;  /* [6, 0.8] beta grows by tau if ||z^k|| > theta ||z^{k-1}|| */
+  double lambda_max;  /* [1e12] box of the outer multiplier lambda */
+  double beta_max;    /* [1e24] cap of beta */
+  double mu_line;     /* [5e3] penalty of the PHR line-limit term */
+  int32_t newton_max_iter; /* [50] trust-region Newton iterations per line solve */
+  double newton_gtol; /* [1e-12] projected-gradient tolerance, times max(1, rho_pq, rho_va) */
+  int32_t max_inner;  /* [1000] inner iterations before a forced outer update */
+  double eps_in0;     /* [1e-2] inner tolerance of outer iteration k: max(tol/2, eps_in0 2^-k) */
+  double tol;         /* [1e-4] primal/dual residual tolerance used by the inner rule */
+  int32_t warm_start; /* [0] line Newton start: 0 flat (mid voltages, zero angles),
+                         1 previous iterate, 2 learned (needs ucac_set_warmstart) */
+  int32_t device;     /* [0] HIP device ordinal */
+} ucac_params;
+
+/* Fill p with the defaults above. */
+void ucac_params_default(ucac_params* p);
+
+/* Validate and copy an instance to the device, cold-start the iterate (flat
+ * voltages, mid-range generation, every unit committed, zero multipliers) and
+ * build the iteration graph.  *out receives a handle the caller frees with
+ * ucac_destroy.  UCAC_E_INVAL: NaN/Inf data, index out of range, a line with
+ * from == to or r = x = 0, pmin > pmax, qmin > qmax, vmin > vmax or vmin <= 0,
+ * min up/down < 1, u0 not in {0,1}, a bus with neither a line nor a generator,
+ * or a bad parameter.  UCAC_E_NOMEM / UCAC_E_DEVICE on allocation / HIP errors. */
+int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle** out);
+
+/* Run all later work of the handle on this HIP stream (a hipStream_t, e.g. the
+ * current torch stream).  NULL selects the handle's own stream. */
+int ucac_set_stream(ucac_handle* h, void* hip_stream);
+
+/* Exactly n_iters inner iterations, each followed by the inner/outer control
+ * (outer update when the inner loop ends).  Does not stop at the tolerance.
+ * Synchronous: returns when the work is done. */
+int ucac_step(ucac_handle* h, int32_t n_iters);
+
+/* Iterate until r_p <= tol and r_d <= tol (UCAC_OK) or until max_iters inner
+ * iterations (UCAC_NOT_CONVERGED).  The stopping iteration is decided on the
+ * device, so the result does not depend on how often the host polls.
+ * *iters_done (may be NULL) receives the iterations run by this call. */
+int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_done);
+
+/* Residuals of the current iterate: r_primal = max |A x + B xbar| over all
+ * coupling rows (the paper's primal infeasibility), r_dual = max |xbar^{l+1} -
+ * xbar^l|, z_inf = max |z|, objective = generation plus commitment cost.
+ * Any output pointer may be NULL. */
+int ucac_residuals(const ucac_handle* h, double* r_primal, double* r_dual, double* z_inf, double* objective);
+
+/* Copy the solution into caller-allocated host arrays (any may be NULL):
+ * p, q, u_on, u_su, u_sd [T][n_gen]; vm, va [T][n_bus] (vm = sqrt(wbar),
+ * va = thetabar, the bus-side duplicates). */
+int ucac_get_solution(const ucac_handle* h, double* p, double* q, int8_t* u_on, int8_t* u_su,
+                      int8_t* u_sd, double* vm, double* va);
+
+/* Full iterate as a flat FP64 array (line x-side, generator x-side, duplicates,
+ * z/y/lambda of every row, then beta, ||z^{k-1}||, k, l, iteration count,
+ * r_p, r_in, r_d, ||z||, converged flag).  With buf == NULL only *bytes is set.
+ * UCAC_E_STATE if *bytes is too small. */
+int ucac_get_state(const ucac_handle* h, void* buf, size_t* bytes);
+
+/* Replace the iterate (resume or inject).  UCAC_E_STATE if bytes differs from
+ * the state size or the buffer holds NaN/Inf. */
+int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes);
+
+/* Newton iterations of the last line solve, per (t, line): [T][n_line]. */
+int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
+
+/* Number of kernels in one inner iteration, in launch order: UC dynamic program,
+ * generators, lines (trust-region Newton), relaxed commitments, buses (with the
+ * line and generator-consensus multipliers), coupling/commitment multipliers,
+ * control (residuals and inner/outer decision), outer lambda update. */
+#define UCAC_N_KERNELS 8
+
+/* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
+ * with every kernel launched on its own and a HIP event recorded on the handle's
+ * stream before and after it; avg_ms[k] (n_slots >= UCAC_N_KERNELS) receives the
+ * mean device time of kernel k per iteration.  Synchronous. */
+int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots);
+
+/* Running totals of the line kernel's work since create or the last reset:
+ * out[0] full evaluations (value, gradient, Hessian), out[1] trial evaluations
+ * (value only), out[2] CG iterations, out[3] Newton iterations.  reset != 0
+ * zeroes them after reading. */
+int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
+
+/* Message of the last error on this handle (or of the last failed create when
+ * h is NULL).  Valid until the next call on the handle. */
+const char* ucac_last_error(const ucac_handle* h);
+
+/* Free the handle and its device memory.  NULL is ignored. */
+void ucac_destroy(ucac_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UCAC_H */

@@ -1,0 +1,311 @@
+// step:opf, line part -- one lane per (line, period).
+//
+// Each lane minimises, over the four end variables x = (v_i, v_j, th_i, th_j) in
+// the box v in [Vmin, Vmax], |th| <= 2 pi, the augmented-Lagrangian terms of the
+// line's eight rows (the four flows of eq:acopf in polar form against their
+// bus-side duplicates, v^2 against wbar and the angles against thetabar) plus a
+// PHR term for each end's MVA limit, by a projected trust-region Newton method:
+// basic trust-region iteration with a Steihaug-Toint truncated CG step on the free
+// variables, projection onto the box and ratio-test acceptance.  The line-limit
+// multipliers nu are then advanced once: nu <- max(0, nu + mu h(x*)).
+//
+// gfx950 mapping: FP64 vector ALU bound.  All Newton state (x, gradient, the 10
+// distinct Hessian entries, CG vectors) lives in VGPRs; every loop over the four
+// variables is unrolled so no array is indexed dynamically; one sincos per
+// function evaluation.  The objective's Hessian is assembled from two per-end
+// Gauss-Newton blocks and one weighted second-derivative block (all four flows
+// share the form a v_i^2 + b v_j^2 + v_i v_j (al cos d + be sin d)), so a full
+// evaluation costs about 200 flops.
+#include "ucac_launch.hpp"
+
+namespace ucac {
+
+namespace {
+
+struct Line {
+  // flow k = a_k vi^2 + b_k vj^2 + vi vj (al_k cos d + be_k sin d)
+  double Gii, Bii, Gij, Bij, Gjj, Bjj, Gji, Bji;
+  double rate2;
+  double lo0, hi0, lo1, hi1;  // voltage boxes; angles are in [-2pi, 2pi]
+  double c[8];
+  double rpq, rva, mu, nu0, nu1;
+};
+
+struct Sym4 {
+  double h00, h01, h02, h03, h11, h12, h13, h22, h23, h33;
+};
+
+__device__ inline void flows4(const Line& L, double vi, double vj, double C, double S, double& f0, double& f1,
+                              double& f2, double& f3) {
+  const double vv = vi * vj, vi2 = vi * vi, vj2 = vj * vj;
+  f0 = L.Gii * vi2 + vv * (L.Gij * C + L.Bij * S);
+  f1 = -L.Bii * vi2 + vv * (-L.Bij * C + L.Gij * S);
+  f2 = L.Gjj * vj2 + vv * (L.Gji * C - L.Bji * S);
+  f3 = -L.Bjj * vj2 + vv * (-L.Bji * C - L.Gji * S);
+}
+
+__device__ inline double objective(const Line& L, const double (&x)[4]) {
+  double S, C;
+  sincos(x[2] - x[3], &S, &C);
+  double f0, f1, f2, f3;
+  flows4(L, x[0], x[1], C, S, f0, f1, f2, f3);
+  const double r0 = f0 - L.c[0], r1 = f1 - L.c[1], r2 = f2 - L.c[2], r3 = f3 - L.c[3];
+  double F = 0.5 * L.rpq * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+  const double r4 = x[0] * x[0] - L.c[4], r5 = x[1] * x[1] - L.c[5];
+  const double r6 = x[2] - L.c[6], r7 = x[3] - L.c[7];
+  F += 0.5 * L.rva * (r4 * r4 + r5 * r5 + r6 * r6 + r7 * r7);
+  const double hf = f0 * f0 + f1 * f1 - L.rate2, ht = f2 * f2 + f3 * f3 - L.rate2;
+  const double tf = fmax(L.nu0 + L.mu * hf, 0.0), tt = fmax(L.nu1 + L.mu * ht, 0.0);
+  F += (tf * tf - L.nu0 * L.nu0) / (2.0 * L.mu) + (tt * tt - L.nu1 * L.nu1) / (2.0 * L.mu);
+  return F;
+}
+
+__device__ inline void rank1(Sym4& H, double w, const double (&v)[4]) {
+  H.h00 += w * v[0] * v[0]; H.h01 += w * v[0] * v[1]; H.h02 += w * v[0] * v[2]; H.h03 += w * v[0] * v[3];
+  H.h11 += w * v[1] * v[1]; H.h12 += w * v[1] * v[2]; H.h13 += w * v[1] * v[3];
+  H.h22 += w * v[2] * v[2]; H.h23 += w * v[2] * v[3]; H.h33 += w * v[3] * v[3];
+}
+
+// value, gradient and Hessian
+__device__ inline double evaluate(const Line& L, const double (&x)[4], double (&g)[4], Sym4& H) {
+  const double vi = x[0], vj = x[1];
+  double S, C;
+  sincos(x[2] - x[3], &S, &C);
+  const double vv = vi * vj;
+  // per-flow (a, b, al, be)
+  const double a[4] = {L.Gii, -L.Bii, 0.0, 0.0};
+  const double b[4] = {0.0, 0.0, L.Gjj, -L.Bjj};
+  const double al[4] = {L.Gij, -L.Bij, L.Gji, -L.Bji};
+  const double be[4] = {L.Bij, L.Gij, -L.Bji, -L.Gji};
+  double f[4], gf[4][4], T[4], Td[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T[k] = al[k] * C + be[k] * S;
+    Td[k] = -al[k] * S + be[k] * C;
+    f[k] = a[k] * vi * vi + b[k] * vj * vj + vv * T[k];
+    gf[k][0] = 2.0 * a[k] * vi + vj * T[k];
+    gf[k][1] = 2.0 * b[k] * vj + vi * T[k];
+    gf[k][2] = vv * Td[k];
+    gf[k][3] = -vv * Td[k];
+  }
+  double w[4];
+  double F = 0.0;
+  H = Sym4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int kp = 2 * m, kq = 2 * m + 1;
+    const double nu = m == 0 ? L.nu0 : L.nu1;
+    const double rP = f[kp] - L.c[kp], rQ = f[kq] - L.c[kq];
+    const double h = f[kp] * f[kp] + f[kq] * f[kq] - L.rate2;
+    const double tm = nu + L.mu * h;
+    const double tp = tm > 0.0 ? tm : 0.0;
+    F += 0.5 * L.rpq * (rP * rP + rQ * rQ) + (tp * tp - nu * nu) / (2.0 * L.mu);
+    w[kp] = L.rpq * rP + 2.0 * tp * f[kp];
+    w[kq] = L.rpq * rQ + 2.0 * tp * f[kq];
+    const double gn = L.rpq + 2.0 * tp;
+    rank1(H, gn, gf[kp]);
+    rank1(H, gn, gf[kq]);
+    if (tm > 0.0) {
+      double gh[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gh[i] = 2.0 * f[kp] * gf[kp][i] + 2.0 * f[kq] * gf[kq][i];
+      rank1(H, L.mu, gh);
+    }
+  }
+  double Aw = 0.0, Bw = 0.0, Tw = 0.0, Tdw = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Aw += w[k] * a[k];
+    Bw += w[k] * b[k];
+    Tw += w[k] * T[k];
+    Tdw += w[k] * Td[k];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) g[i] = w[0] * gf[0][i] + w[1] * gf[1][i] + w[2] * gf[2][i] + w[3] * gf[3][i];
+  // weighted second derivatives of the flows
+  H.h00 += 2.0 * Aw;      H.h01 += Tw;           H.h02 += vj * Tdw;  H.h03 -= vj * Tdw;
+  H.h11 += 2.0 * Bw;      H.h12 += vi * Tdw;     H.h13 -= vi * Tdw;
+  H.h22 -= vv * Tw;       H.h23 += vv * Tw;      H.h33 -= vv * Tw;
+  // voltage-square and angle rows
+  const double r4 = vi * vi - L.c[4], r5 = vj * vj - L.c[5];
+  const double r6 = x[2] - L.c[6], r7 = x[3] - L.c[7];
+  F += 0.5 * L.rva * (r4 * r4 + r5 * r5 + r6 * r6 + r7 * r7);
+  g[0] += L.rva * r4 * 2.0 * vi;
+  g[1] += L.rva * r5 * 2.0 * vj;
+  g[2] += L.rva * r6;
+  g[3] += L.rva * r7;
+  H.h00 += L.rva * (4.0 * vi * vi + 2.0 * r4);
+  H.h11 += L.rva * (4.0 * vj * vj + 2.0 * r5);
+  H.h22 += L.rva;
+  H.h33 += L.rva;
+  return F;
+}
+
+__device__ inline void symv(const Sym4& H, const double (&v)[4], double (&out)[4]) {
+  out[0] = H.h00 * v[0] + H.h01 * v[1] + H.h02 * v[2] + H.h03 * v[3];
+  out[1] = H.h01 * v[0] + H.h11 * v[1] + H.h12 * v[2] + H.h13 * v[3];
+  out[2] = H.h02 * v[0] + H.h12 * v[1] + H.h22 * v[2] + H.h23 * v[3];
+  out[3] = H.h03 * v[0] + H.h13 * v[1] + H.h23 * v[2] + H.h33 * v[3];
+}
+
+__device__ inline double dot(const double (&a)[4], const double (&b)[4]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+// Steihaug-Toint CG on the free variables (mask fr), radius delta.
+__device__ inline void steihaug(const Sym4& H, const double (&g)[4], const double (&fr)[4], int nf, double delta,
+                                double (&out)[4], int& cg_its) {
+  double z[4] = {0.0, 0.0, 0.0, 0.0}, r[4], d[4], Hd[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { r[i] = fr[i] * g[i]; d[i] = -r[i]; }
+  double rr = dot(r, r);
+  const double tol = 1e-12 * sqrt(rr);
+  for (int j = 0; j < nf; ++j) {
+    ++cg_its;
+    symv(H, d, Hd);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Hd[i] *= fr[i];
+    const double dHd = dot(d, Hd);
+    double zn[4];
+    const double alpha = rr / dHd;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zn[i] = z[i] + alpha * d[i];
+    if (dHd <= 0.0 || sqrt(dot(zn, zn)) >= delta) {
+      // to the boundary along d: ||z + tau d|| = delta
+      const double zd = dot(z, d), dd = dot(d, d), zz = dot(z, z);
+      const double tau = (-zd + sqrt(zd * zd + dd * (delta * delta - zz))) / dd;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[i] = z[i] + tau * d[i];
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { r[i] += alpha * Hd[i]; z[i] = zn[i]; }
+    const double rr_new = dot(r, r);
+    if (sqrt(rr_new) <= tol) break;
+    const double beta = rr_new / rr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = -r[i] + beta * d[i];
+    rr = rr_new;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = z[i];
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p) {
+  if (s.ctl->halt) return;
+  const int TL = n.T * n.L;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const bool active = idx < TL;
+  int n_eval = 0, n_trial = 0, n_cg = 0, it = 0;
+  if (active) {
+  const int t = idx / n.L, l = idx - t * n.L;
+  const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
+
+  Line L;
+  L.Gii = n.adm[0 * n.L + l]; L.Bii = n.adm[1 * n.L + l]; L.Gij = n.adm[2 * n.L + l]; L.Bij = n.adm[3 * n.L + l];
+  L.Gjj = n.adm[4 * n.L + l]; L.Bjj = n.adm[5 * n.L + l]; L.Gji = n.adm[6 * n.L + l]; L.Bji = n.adm[7 * n.L + l];
+  const double rate = n.rate[l];
+  L.rate2 = rate * rate;
+  L.lo0 = n.vmin[n.from[l]]; L.hi0 = n.vmax[n.from[l]];
+  L.lo1 = n.vmin[n.to[l]]; L.hi1 = n.vmax[n.to[l]];
+  L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu;
+  L.nu0 = s.nuf[idx]; L.nu1 = s.nut[idx];
+  {
+    const double xb[8] = {s.Pbf[idx], s.Qbf[idx], s.Pbt[idx], s.Qbt[idx], s.wb[bi], s.wb[bj], s.thb[bi], s.thb[bj]};
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double rho = r < 4 ? p.rho_pq : p.rho_va;
+      L.c[r] = xb[r] - s.zB[r * TL + idx] - s.yB[r * TL + idx] / rho;
+    }
+  }
+  const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
+  const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
+
+  double x[4];
+  if (p.warm_start == 1) {
+    x[0] = s.vf[idx]; x[1] = s.vt[idx]; x[2] = s.thf[idx]; x[3] = s.tht[idx];
+  } else {
+    x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
+
+  double g[4];
+  Sym4 H;
+  double F = evaluate(L, x, g, H);
+  n_eval = 1;
+  double delta = 1.0;
+  for (it = 0; it < p.newton_max_iter; ++it) {
+    double fr[4];
+    int nf = 0;
+    double pg = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool out = (x[i] <= lo[i] && g[i] > 0.0) || (x[i] >= hi[i] && g[i] < 0.0);
+      fr[i] = out ? 0.0 : 1.0;
+      nf += out ? 0 : 1;
+      pg = out ? pg : fmax(pg, fabs(g[i]));
+    }
+    if (pg <= p.gtol) break;
+    double d[4];
+    steihaug(H, g, fr, nf, delta, d, n_cg);
+    double xt[4], sv[4];
+    double sinf = 0.0, xinf = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xt[i] = clampd(x[i] + d[i], lo[i], hi[i]);
+      sv[i] = xt[i] - x[i];
+      sinf = fmax(sinf, fabs(sv[i]));
+      xinf = fmax(xinf, fabs(x[i]));
+    }
+    if (sinf <= 1e-15 * (1.0 + xinf)) break;
+    double Hs[4];
+    symv(H, sv, Hs);
+    const double pred = -(dot(g, sv) + 0.5 * dot(sv, Hs));
+    const double Ft = objective(L, xt);
+    ++n_trial;
+    const double ratio = pred > 0.0 ? (pred <= 1e-12 * fabs(F) ? 1.0 : (F - Ft) / pred) : -1.0;
+    const double snorm = sqrt(dot(sv, sv));
+    if (ratio < 0.25) delta = 0.25 * snorm;
+    else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
+    if (ratio >= 1e-4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = xt[i];
+      F = evaluate(L, x, g, H);
+      ++n_eval;
+    }
+  }
+
+  double S, C;
+  sincos(x[2] - x[3], &S, &C);
+  double f0, f1, f2, f3;
+  flows4(L, x[0], x[1], C, S, f0, f1, f2, f3);
+  s.vf[idx] = x[0]; s.vt[idx] = x[1]; s.thf[idx] = x[2]; s.tht[idx] = x[3];
+  s.pf[idx] = f0; s.qf[idx] = f1; s.pt[idx] = f2; s.qt[idx] = f3;
+  s.nuf[idx] = fmax(0.0, L.nu0 + L.mu * (f0 * f0 + f1 * f1 - L.rate2));
+  s.nut[idx] = fmax(0.0, L.nu1 + L.mu * (f2 * f2 + f3 * f3 - L.rate2));
+  s.br_iters[idx] = it;
+  }
+  // work counters: one wave-level sum and one atomic per wave and counter
+  unsigned long long c[4] = {(unsigned long long)n_eval, (unsigned long long)n_trial, (unsigned long long)n_cg,
+                             (unsigned long long)it};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicAdd(&s.br_count[k], c[k]);
+  }
+}
+
+void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const int TL = n.T * n.L;
+  if (TL == 0) return;
+  hipLaunchKernelGGL(k_branch, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+}
+
+}  // namespace ucac

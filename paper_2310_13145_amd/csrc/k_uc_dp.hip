@@ -1,0 +1,116 @@
+// step:uc -- one dynamic program per generator (Sec. III-B, Alg. dp_algo).
+//
+// One 64-lane wavefront per generator.  The lanes build the cost table
+// L^UC_{g,t}(s', s) for all periods in parallel into LDS (4 doubles per period),
+// then lane 0 runs the backward stay/switch induction (keep_formula,
+// switch_formula) and the forward reconstruction from one decision bit per
+// (period, state) -- O(T) extra space instead of the paper's stored O(T^2)
+// trajectories -- and the lanes write u_on/u_su/u_sd back, one period each.
+//
+// This file is compiled with -ffp-contract=off: the table entries and the
+// stay/switch sums are plain IEEE additions and products in a fixed order, so a
+// commitment is decided on exactly the same numbers as in any other plain FP64
+// evaluation of the same expressions.
+#include "ucac_launch.hpp"
+
+namespace ucac {
+
+// L^UC(s', s): commitment costs plus y (u - ubar + z) + rho/2 (u - ubar + z)^2
+// over (on, su, sd), with su = max(0, s - s'), sd = max(0, s' - s).
+__device__ inline double uc_table_entry(double cnl, double csu, double csd, double rho, int sp, int s,
+                                        const double* ub, const double* z, const double* y) {
+  const int usu = s > sp ? 1 : 0;
+  const int usd = sp > s ? 1 : 0;
+  double L = cnl * (double)s + csu * (double)usu + csd * (double)usd;
+  const double u[3] = {(double)s, (double)usu, (double)usd};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double r = (u[k] - ub[k]) + z[k];
+    L += y[k] * r + 0.5 * rho * r * r;
+  }
+  return L;
+}
+
+__global__ void __launch_bounds__(64) k_uc_dp(Net n, State s, Par p) {
+  if (s.ctl->halt) return;
+  const int g = blockIdx.x;
+  const int T = n.T, G = n.G;
+  const int lane = threadIdx.x;
+  extern __shared__ double lds[];
+  double* Lt = lds;                       // [T][2][2]
+  double* c = Lt + 4 * T;                 // [T+2][2], c[T+1][*] = 0
+  unsigned char* dec = (unsigned char*)(c + 2 * (T + 2));  // [T+2][2]
+  signed char* u = (signed char*)(dec + 2 * (T + 2));     // [T]
+
+  const double cnl = n.cnl[g], csu = n.csu[g], csd = n.csd[g], rho = p.rho_uc;
+  const int TGs = T * G;
+  for (int t = lane; t < T; t += 64) {
+    const int k = t * G + g;
+    const double ub[3] = {s.ubon[k], s.ubsu[k], s.ubsd[k]};
+    const double z[3] = {s.zG[RG_U1 * TGs + k], s.zG[RG_U2 * TGs + k], s.zG[RG_U3 * TGs + k]};
+    const double y[3] = {s.yG[RG_U1 * TGs + k], s.yG[RG_U2 * TGs + k], s.yG[RG_U3 * TGs + k]};
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int ss = 0; ss < 2; ++ss) Lt[(t * 2 + sp) * 2 + ss] = uc_table_entry(cnl, csu, csd, rho, sp, ss, ub, z, y);
+  }
+  __syncthreads();
+
+  if (lane == 0) {
+    const int u0 = n.u0[g], TU = n.tu[g], TD = n.td[g];
+    int hold = u0 ? n.lon[g] : n.loff[g];
+    hold = hold > T ? T : (hold < 0 ? 0 : hold);
+    // 1-based periods: entry of period t at Lt[(t-1)*4 + sp*2 + s]
+    c[(T + 1) * 2 + 0] = 0.0;
+    c[(T + 1) * 2 + 1] = 0.0;
+    for (int t = T; t >= 1 && t > hold; --t) {
+      for (int ss = 0; ss < 2; ++ss) {
+        const double stay = Lt[((t - 1) * 2 + ss) * 2 + ss] + c[(t + 1) * 2 + ss];
+        const int ns = 1 - ss;
+        const int Tm = ns ? TU : TD;
+        double sw = Lt[((t - 1) * 2 + ss) * 2 + ns];
+        const int last = (t + Tm - 1) < T ? (t + Tm - 1) : T;
+        for (int tp = t + 1; tp <= last; ++tp) sw += Lt[((tp - 1) * 2 + ns) * 2 + ns];
+        const int nxt = t + Tm;
+        sw += (nxt <= T) ? c[nxt * 2 + ns] : 0.0;
+        const bool keep = stay <= sw;
+        c[t * 2 + ss] = keep ? stay : sw;
+        dec[t * 2 + ss] = keep ? 0 : 1;
+      }
+    }
+    int t = 1, st = u0;
+    for (int k = 1; k <= hold; ++k) u[k - 1] = (signed char)u0;
+    t = hold + 1;
+    while (t <= T) {
+      if (dec[t * 2 + st] == 0) {
+        u[t - 1] = (signed char)st;
+        ++t;
+      } else {
+        const int ns = 1 - st;
+        const int Tm = ns ? TU : TD;
+        for (int k = t; k <= t + Tm - 1 && k <= T; ++k) u[k - 1] = (signed char)ns;
+        t += Tm;
+        st = ns;
+      }
+    }
+  }
+  __syncthreads();
+
+  const int u0 = n.u0[g];
+  for (int t = lane; t < T; t += 64) {
+    const int k = t * G + g;
+    const int cur = u[t];
+    const int prev = t == 0 ? u0 : u[t - 1];
+    s.uon[k] = (double)cur;
+    s.usu[k] = cur > prev ? 1.0 : 0.0;
+    s.usd[k] = prev > cur ? 1.0 : 0.0;
+  }
+}
+
+void launch_uc_dp(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  if (n.G == 0) return;
+  const size_t lds = sizeof(double) * (4 * (size_t)n.T + 2 * ((size_t)n.T + 2)) + 2 * ((size_t)n.T + 2) + (size_t)n.T;
+  hipLaunchKernelGGL(k_uc_dp, dim3(n.G), dim3(64), lds, st, n, s, p);
+}
+
+}  // namespace ucac

@@ -1,0 +1,662 @@
+// Host side of the C-ABI in include/ucac.h: input validation, device layout,
+// cold start, the captured iteration graph and the control loop of ucac_solve.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ucac.h"
+#include "ucac_launch.hpp"
+
+using namespace ucac;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Poll the device-side status every this many iterations in ucac_solve; the
+// next chunk is already queued while the host reads the previous one.
+constexpr int SOLVE_CHUNK = 32;
+
+struct HostGen {
+  std::vector<double> k2, k1, cnl, csu, csd;
+  std::vector<int> u0;
+};
+
+}  // namespace
+
+struct ucac_handle {
+  int N = 0, L = 0, G = 0, T = 0, ref = 0;
+  ucac_params par{};
+  hipStream_t own = nullptr, stream = nullptr;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  Net net{};
+  State st{};
+  Par kp{};
+  size_t n_state = 0;  // doubles
+  double* d_state = nullptr;
+  Ctl* d_ctl = nullptr;
+  Ctl* h_ctl = nullptr;      // pinned staging of the control block
+  double* h_sc = nullptr;    // pinned staging of the scalars
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_poll = nullptr;
+  HostGen hg;
+  std::string err;
+};
+
+namespace {
+
+int fail(ucac_handle* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf; else g_create_error = buf;
+  return code;
+}
+
+#define HIP_OR(h, call)                                                                             \
+  do {                                                                                              \
+    hipError_t _e = (call);                                                                         \
+    if (_e != hipSuccess) return fail(h, UCAC_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+size_t state_doubles(size_t N, size_t L, size_t G, size_t T) {
+  return T * L * (10 + 4 + 3 * NRB) + T * G * (11 + 5 + 3 * NRG) + T * N * 2 + NSC;
+}
+
+int validate(const ucac_network* n, const ucac_params* p) {
+  if (!n || !p) return fail(nullptr, UCAC_E_INVAL, "null network or params");
+  if (n->n_bus < 1 || n->n_line < 0 || n->n_gen < 0 || n->T < 1)
+    return fail(nullptr, UCAC_E_INVAL, "bad sizes n_bus=%d n_line=%d n_gen=%d T=%d", n->n_bus, n->n_line, n->n_gen, n->T);
+  const long long TL = (long long)n->T * n->n_line, TN = (long long)n->T * n->n_bus, TG = (long long)n->T * n->n_gen;
+  if (TL * NRB > 0x7fffffffLL || TN > 0x7fffffffLL || TG * NRG > 0x7fffffffLL)
+    return fail(nullptr, UCAC_E_INVAL, "instance too large for 32-bit item indices");
+  if (n->ref_bus < 0 || n->ref_bus >= n->n_bus) return fail(nullptr, UCAC_E_INVAL, "ref_bus %d out of range", n->ref_bus);
+  if (!(n->base_mva > 0.0) || !std::isfinite(n->base_mva)) return fail(nullptr, UCAC_E_INVAL, "base_mva must be positive");
+  const int N = n->n_bus, L = n->n_line, G = n->n_gen;
+  if (L > 0 && (!n->line_from || !n->line_to || !n->line_r || !n->line_x || !n->line_b || !n->line_rate))
+    return fail(nullptr, UCAC_E_INVAL, "null line array");
+  if (!n->bus_gs || !n->bus_bs || !n->bus_vmin || !n->bus_vmax || !n->load_p || !n->load_q)
+    return fail(nullptr, UCAC_E_INVAL, "null bus array");
+  if (G > 0 && (!n->gen_bus || !n->gen_pmin || !n->gen_pmax || !n->gen_qmin || !n->gen_qmax || !n->gen_c2 ||
+                !n->gen_c1 || !n->gen_cnl || !n->gen_csu || !n->gen_csd || !n->gen_ru || !n->gen_rd || !n->gen_su ||
+                !n->gen_sd || !n->gen_min_up || !n->gen_min_dn || !n->gen_u0 || !n->gen_init_on ||
+                !n->gen_init_off || !n->gen_p0))
+    return fail(nullptr, UCAC_E_INVAL, "null generator array");
+  std::vector<int> deg(N, 0);
+  for (int l = 0; l < L; ++l) {
+    const int i = n->line_from[l], j = n->line_to[l];
+    if (i < 0 || i >= N || j < 0 || j >= N || i == j) return fail(nullptr, UCAC_E_INVAL, "line %d has bad end buses (%d, %d)", l, i, j);
+    if (!finite_all(&n->line_r[l], 1) || !finite_all(&n->line_x[l], 1) || !finite_all(&n->line_b[l], 1) ||
+        !finite_all(&n->line_rate[l], 1))
+      return fail(nullptr, UCAC_E_INVAL, "line %d has non-finite data", l);
+    if (n->line_r[l] * n->line_r[l] + n->line_x[l] * n->line_x[l] <= 0.0) return fail(nullptr, UCAC_E_INVAL, "line %d has zero impedance", l);
+    if (!(n->line_rate[l] > 0.0)) return fail(nullptr, UCAC_E_INVAL, "line %d has a non-positive rating", l);
+    deg[i]++; deg[j]++;
+  }
+  if (!finite_all(n->bus_gs, N) || !finite_all(n->bus_bs, N) || !finite_all(n->bus_vmin, N) || !finite_all(n->bus_vmax, N))
+    return fail(nullptr, UCAC_E_INVAL, "non-finite bus data");
+  for (int i = 0; i < N; ++i)
+    if (!(n->bus_vmin[i] > 0.0) || n->bus_vmin[i] > n->bus_vmax[i]) return fail(nullptr, UCAC_E_INVAL, "bus %d has bad voltage bounds", i);
+  if (!finite_all(n->load_p, (size_t)TN) || !finite_all(n->load_q, (size_t)TN)) return fail(nullptr, UCAC_E_INVAL, "non-finite load");
+  for (int g = 0; g < G; ++g) {
+    const int b = n->gen_bus[g];
+    if (b < 0 || b >= N) return fail(nullptr, UCAC_E_INVAL, "generator %d at bus %d out of range", g, b);
+    const double* d[] = {&n->gen_pmin[g], &n->gen_pmax[g], &n->gen_qmin[g], &n->gen_qmax[g], &n->gen_c2[g], &n->gen_c1[g],
+                         &n->gen_cnl[g], &n->gen_csu[g], &n->gen_csd[g], &n->gen_ru[g], &n->gen_rd[g], &n->gen_su[g],
+                         &n->gen_sd[g], &n->gen_p0[g]};
+    for (const double* v : d)
+      if (!std::isfinite(*v)) return fail(nullptr, UCAC_E_INVAL, "generator %d has non-finite data", g);
+    if (n->gen_pmin[g] > n->gen_pmax[g] || n->gen_pmax[g] < 0.0) return fail(nullptr, UCAC_E_INVAL, "generator %d: pmin > pmax or pmax < 0", g);
+    if (n->gen_qmin[g] > n->gen_qmax[g]) return fail(nullptr, UCAC_E_INVAL, "generator %d: qmin > qmax", g);
+    if (n->gen_c2[g] < 0.0) return fail(nullptr, UCAC_E_INVAL, "generator %d: c2 < 0 (non-convex cost)", g);
+    if (n->gen_min_up[g] < 1 || n->gen_min_dn[g] < 1) return fail(nullptr, UCAC_E_INVAL, "generator %d: min up/down < 1", g);
+    if (n->gen_u0[g] != 0 && n->gen_u0[g] != 1) return fail(nullptr, UCAC_E_INVAL, "generator %d: u0 not in {0,1}", g);
+    if (n->gen_init_on[g] < 0 || n->gen_init_off[g] < 0) return fail(nullptr, UCAC_E_INVAL, "generator %d: negative initial hold", g);
+    deg[b]++;
+  }
+  for (int i = 0; i < N; ++i)
+    if (deg[i] == 0) return fail(nullptr, UCAC_E_INVAL, "bus %d has neither a line nor a generator", i);
+  const double pos[] = {p->rho_pq, p->rho_va, p->rho_uc, p->rho_cpl, p->beta0, p->tau, p->lambda_max, p->beta_max, p->mu_line};
+  for (double v : pos)
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(nullptr, UCAC_E_INVAL, "penalty parameters must be positive and finite");
+  if (!(p->theta > 0.0) || !(p->newton_gtol >= 0.0) || !(p->eps_in0 >= 0.0) || !(p->tol > 0.0) || p->newton_max_iter < 0 ||
+      p->max_inner < 1 || p->warm_start < 0 || p->warm_start > 1)
+    return fail(nullptr, UCAC_E_INVAL, "bad iteration parameters");
+  return UCAC_OK;
+}
+
+struct Arena {
+  char* base;
+  size_t off;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * n;
+    return p;
+  }
+};
+
+// Carve every device array out of one allocation.  With base == nullptr only the
+// size is computed.
+size_t carve(ucac_handle* h, char* base) {
+  const size_t N = h->N, L = h->L, G = h->G, T = h->T;
+  Arena a{base, 0};
+  Net& n = h->net;
+  State& s = h->st;
+  n.N = h->N; n.L = h->L; n.G = h->G; n.T = h->T; n.ref = h->ref;
+  n.from = a.take<int>(L); n.to = a.take<int>(L);
+  n.adm = a.take<double>(8 * L); n.rate = a.take<double>(L);
+  n.gs = a.take<double>(N); n.bs = a.take<double>(N); n.vmin = a.take<double>(N); n.vmax = a.take<double>(N);
+  n.Pd = a.take<double>(T * N); n.Qd = a.take<double>(T * N);
+  n.inc_start = a.take<int>(N + 1); n.inc_code = a.take<int>(2 * L);
+  n.gen_start = a.take<int>(N + 1); n.gen_list = a.take<int>(G);
+  n.pmin = a.take<double>(G); n.pmax = a.take<double>(G); n.qmin = a.take<double>(G); n.qmax = a.take<double>(G);
+  n.k2 = a.take<double>(G); n.k1 = a.take<double>(G); n.cnl = a.take<double>(G); n.csu = a.take<double>(G);
+  n.csd = a.take<double>(G); n.ru = a.take<double>(G); n.rd = a.take<double>(G); n.su = a.take<double>(G);
+  n.sd = a.take<double>(G); n.p0 = a.take<double>(G);
+  n.tu = a.take<int>(G); n.td = a.take<int>(G); n.u0 = a.take<int>(G); n.lon = a.take<int>(G); n.loff = a.take<int>(G);
+  h->d_state = a.take<double>(h->n_state);
+  s.ub_nxt = a.take<double>(3 * T * G);
+  s.br_iters = a.take<int>(T * L);
+  s.br_count = a.take<unsigned long long>(4);
+  h->d_ctl = a.take<Ctl>(1);
+  s.ctl = h->d_ctl;
+  // state views (the state format of ucac_get_state)
+  double* c = h->d_state;
+  auto nx = [&](size_t k) { double* p = c; if (c) c += k; return p; };
+  const size_t TL = T * L, TG = T * G, TN = T * N;
+  s.vf = nx(TL); s.vt = nx(TL); s.thf = nx(TL); s.tht = nx(TL); s.pf = nx(TL); s.qf = nx(TL); s.pt = nx(TL); s.qt = nx(TL);
+  s.nuf = nx(TL); s.nut = nx(TL);
+  s.p = nx(TG); s.q = nx(TG); s.s = nx(6 * TG); s.uon = nx(TG); s.usu = nx(TG); s.usd = nx(TG);
+  s.wb = nx(TN); s.thb = nx(TN);
+  s.Pbf = nx(TL); s.Qbf = nx(TL); s.Pbt = nx(TL); s.Qbt = nx(TL);
+  s.pb = nx(TG); s.qb = nx(TG); s.ubon = nx(TG); s.ubsu = nx(TG); s.ubsd = nx(TG);
+  s.zB = nx(NRB * TL); s.yB = nx(NRB * TL); s.lB = nx(NRB * TL);
+  s.zG = nx(NRG * TG); s.yG = nx(NRG * TG); s.lG = nx(NRG * TG);
+  s.sc = nx(NSC);
+  return a.off;
+}
+
+// Cold start (the initialisation of the ACOPF variables and an all-committed
+// schedule): mid-range v, p, q; zero angles; flows of the flat voltages;
+// duplicates equal to their originals; slacks at their feasible values;
+// multipliers zero; beta = beta0.
+void cold_start(const ucac_network* n, const std::vector<double>& adm, const ucac_params& par, std::vector<double>& S) {
+  const size_t N = n->n_bus, L = n->n_line, G = n->n_gen, T = n->T;
+  const size_t TL = T * L, TG = T * G, TN = T * N;
+  S.assign(state_doubles(N, L, G, T), 0.0);
+  double* c = S.data();
+  auto nx = [&](size_t k) { double* p = c; c += k; return p; };
+  double *vf = nx(TL), *vt = nx(TL), *thf = nx(TL), *tht = nx(TL), *pf = nx(TL), *qf = nx(TL), *pt = nx(TL), *qt = nx(TL);
+  nx(2 * TL);  // nu
+  double *p = nx(TG), *q = nx(TG), *s = nx(6 * TG), *uon = nx(TG), *usu = nx(TG), *usd = nx(TG);
+  double *wb = nx(TN), *thb = nx(TN);
+  double *Pbf = nx(TL), *Qbf = nx(TL), *Pbt = nx(TL), *Qbt = nx(TL);
+  double *pb = nx(TG), *qb = nx(TG), *ubon = nx(TG), *ubsu = nx(TG), *ubsd = nx(TG);
+  nx(3 * NRB * TL + 3 * NRG * TG);
+  double* sc = nx(NSC);
+  for (size_t t = 0; t < T; ++t) {
+    for (size_t l = 0; l < L; ++l) {
+      const size_t k = t * L + l;
+      const int i = n->line_from[l], j = n->line_to[l];
+      const double vi = 0.5 * (n->bus_vmin[i] + n->bus_vmax[i]), vj = 0.5 * (n->bus_vmin[j] + n->bus_vmax[j]);
+      const double* A = &adm[0];
+      const double Gii = A[0 * L + l], Bii = A[1 * L + l], Gij = A[2 * L + l], Bij = A[3 * L + l];
+      const double Gjj = A[4 * L + l], Bjj = A[5 * L + l], Gji = A[6 * L + l], Bji = A[7 * L + l];
+      // zero angle difference: cos = 1, sin = 0
+      vf[k] = vi; vt[k] = vj; thf[k] = 0.0; tht[k] = 0.0;
+      pf[k] = Gii * vi * vi + vi * vj * Gij;
+      qf[k] = -Bii * vi * vi - vi * vj * Bij;
+      pt[k] = Gjj * vj * vj + vi * vj * Gji;
+      qt[k] = -Bjj * vj * vj - vi * vj * Bji;
+      Pbf[k] = pf[k]; Qbf[k] = qf[k]; Pbt[k] = pt[k]; Qbt[k] = qt[k];
+    }
+    for (size_t i = 0; i < N; ++i) {
+      const double v = 0.5 * (n->bus_vmin[i] + n->bus_vmax[i]);
+      wb[t * N + i] = v * v;
+      thb[t * N + i] = 0.0;
+    }
+    for (size_t g = 0; g < G; ++g) {
+      const size_t k = t * G + g;
+      const double qlo = std::fmin(0.0, n->gen_qmin[g]), qhi = std::fmax(0.0, n->gen_qmax[g]);
+      p[k] = 0.5 * n->gen_pmax[g];
+      q[k] = 0.5 * (qlo + qhi);
+      pb[k] = p[k]; qb[k] = q[k];
+      const int prev = t == 0 ? n->gen_u0[g] : 1;
+      uon[k] = 1.0; usu[k] = prev == 0 ? 1.0 : 0.0; usd[k] = 0.0;
+      ubon[k] = uon[k]; ubsu[k] = usu[k]; ubsd[k] = usd[k];
+    }
+  }
+  for (size_t t = 0; t < T; ++t)
+    for (size_t g = 0; g < G; ++g) {
+      const size_t k = t * G + g;
+      const double pbp = t == 0 ? n->gen_p0[g] : pb[k - G];
+      const double uonp = t == 0 ? (double)n->gen_u0[g] : ubon[k - G];
+      const double pv = p[k], qv = q[k], u = ubon[k];
+      s[0 * TG + k] = std::fmax(0.0, pv - n->gen_pmin[g] * u);
+      s[1 * TG + k] = std::fmax(0.0, n->gen_pmax[g] * u - pv);
+      s[2 * TG + k] = std::fmax(0.0, qv - n->gen_qmin[g] * u);
+      s[3 * TG + k] = std::fmax(0.0, n->gen_qmax[g] * u - qv);
+      s[4 * TG + k] = std::fmax(0.0, pv - pbp + n->gen_rd[g] * u + n->gen_sd[g] * ubsd[k]);
+      s[5 * TG + k] = std::fmax(0.0, -(pv - pbp) + n->gen_ru[g] * uonp + n->gen_su[g] * ubsu[k]);
+    }
+  sc[SC_BETA] = par.beta0;
+  sc[SC_ZPREV] = INFINITY;
+}
+
+Par kernel_params(const ucac_params& p) {
+  Par k;
+  k.rho_pq = p.rho_pq; k.rho_va = p.rho_va; k.rho_uc = p.rho_uc; k.rho_cpl = p.rho_cpl; k.mu = p.mu_line;
+  k.gtol = p.newton_gtol * std::fmax(1.0, std::fmax(p.rho_pq, p.rho_va));
+  k.tau = p.tau; k.theta = p.theta; k.lambda_max = p.lambda_max; k.beta_max = p.beta_max; k.eps_in0 = p.eps_in0;
+  k.newton_max_iter = p.newton_max_iter; k.max_inner = p.max_inner; k.warm_start = p.warm_start;
+  return k;
+}
+
+// Launch one inner iteration; returns the first launch error (with the kernel's name).
+hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
+  struct Step { const char* name; void (*fn)(const Net&, const State&, const Par&, hipStream_t); };
+  static const Step steps[] = {
+      {"uc_dp", launch_uc_dp},          // step:uc
+      {"gen", launch_gen},              // step:opf (generators)
+      {"branch", launch_branch},        // step:opf (lines)
+      {"ubar", launch_ubar},            // step:uc_bar  (reads the previous pbar)
+      {"bus", launch_bus},              // step:opf_bar (reads the previous ubar); line/G rows' z, y
+      {"gen_dual", launch_gen_dual},    // z, y of coupling and commitment rows
+      {"finalize", launch_finalize},    // residuals, inner/outer decision
+      {"lambda", launch_lambda},        // step:outer lambda update when decided
+  };
+  for (const Step& k : steps) {
+    k.fn(h->net, h->st, h->kp, st);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      if (where) *where = k.name;
+      return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// One kernel of the iteration by index (the order of enqueue_iteration).
+hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where) {
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
+  static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_gen_dual, launch_finalize, launch_lambda};
+  fns[k](h->net, h->st, h->kp, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess && where) *where = names[k];
+  return e;
+}
+
+int build_graph(ucac_handle* h) {
+  if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  (void)hipGetLastError();
+  HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
+  const char* where = "";
+  const hipError_t le = enqueue_iteration(h, h->own, &where);
+  const hipError_t ce = hipStreamEndCapture(h->own, &h->graph);
+  if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
+  if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+  HIP_OR(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  return UCAC_OK;
+}
+
+// Write the host-owned control fields (never inside a captured graph).
+int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
+  std::memset(h->h_ctl, 0, sizeof(Ctl));
+  h->h_ctl->stop_at_tol = stop_at_tol;
+  h->h_ctl->tol = tol;
+  HIP_OR(h, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  return UCAC_OK;
+}
+
+int read_status(ucac_handle* h) {
+  HIP_OR(h, hipMemcpyAsync(h->h_sc, h->st.sc, sizeof(double) * NSC, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR(h, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  return UCAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ucac_params_default(ucac_params* p) {
+  if (!p) return;
+  p->rho_pq = 5e3; p->rho_va = 1e4; p->rho_uc = 1e5; p->rho_cpl = 5e3;
+  p->beta0 = 1e5; p->tau = 6.0; p->theta = 0.8; p->lambda_max = 1e12; p->beta_max = 1e24; p->mu_line = 5e3;
+  p->newton_max_iter = 50; p->newton_gtol = 1e-12;
+  p->max_inner = 1000; p->eps_in0 = 1e-2; p->tol = 1e-4;
+  p->warm_start = 0; p->device = 0;
+}
+
+int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle** out) {
+  if (!out) return fail(nullptr, UCAC_E_INVAL, "null output handle");
+  *out = nullptr;
+  int rc = validate(net, params);
+  if (rc != UCAC_OK) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, UCAC_E_DEVICE, "no HIP device");
+  if (params->device < 0 || params->device >= ndev) return fail(nullptr, UCAC_E_INVAL, "device %d out of range", params->device);
+  if (hipSetDevice(params->device) != hipSuccess) return fail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed");
+
+  ucac_handle* h = new ucac_handle();
+  h->N = net->n_bus; h->L = net->n_line; h->G = net->n_gen; h->T = net->T; h->ref = net->ref_bus;
+  h->par = *params;
+  const size_t N = h->N, L = h->L, G = h->G, T = h->T;
+  h->n_state = state_doubles(N, L, G, T);
+
+  // host copies in device layout
+  std::vector<int> from(net->line_from, net->line_from + L), to(net->line_to, net->line_to + L);
+  std::vector<double> adm(8 * L), rate(net->line_rate, net->line_rate + L);
+  for (size_t l = 0; l < L; ++l) {
+    const double r = net->line_r[l], x = net->line_x[l], b = net->line_b[l];
+    const double den = r * r + x * x, gs = r / den, bs = -x / den;
+    adm[0 * L + l] = gs; adm[1 * L + l] = bs + 0.5 * b; adm[2 * L + l] = -gs; adm[3 * L + l] = -bs;
+    adm[4 * L + l] = gs; adm[5 * L + l] = bs + 0.5 * b; adm[6 * L + l] = -gs; adm[7 * L + l] = -bs;
+  }
+  std::vector<int> inc_start(N + 1, 0), inc_code(2 * L), gen_start(N + 1, 0), gen_list(G);
+  for (size_t l = 0; l < L; ++l) { inc_start[from[l] + 1]++; inc_start[to[l] + 1]++; }
+  for (size_t i = 0; i < N; ++i) inc_start[i + 1] += inc_start[i];
+  {
+    std::vector<int> fill(N, 0);
+    for (size_t l = 0; l < L; ++l) {
+      inc_code[inc_start[from[l]] + fill[from[l]]++] = (int)(2 * l);
+      inc_code[inc_start[to[l]] + fill[to[l]]++] = (int)(2 * l + 1);
+    }
+  }
+  for (size_t g = 0; g < G; ++g) gen_start[net->gen_bus[g] + 1]++;
+  for (size_t i = 0; i < N; ++i) gen_start[i + 1] += gen_start[i];
+  {
+    std::vector<int> fill(N, 0);
+    for (size_t g = 0; g < G; ++g) gen_list[gen_start[net->gen_bus[g]] + fill[net->gen_bus[g]]++] = (int)g;
+  }
+  const double base = net->base_mva;
+  h->hg.k2.resize(G); h->hg.k1.resize(G);
+  for (size_t g = 0; g < G; ++g) { h->hg.k2[g] = net->gen_c2[g] * base * base; h->hg.k1[g] = net->gen_c1[g] * base; }
+  h->hg.cnl.assign(net->gen_cnl, net->gen_cnl + G);
+  h->hg.csu.assign(net->gen_csu, net->gen_csu + G);
+  h->hg.csd.assign(net->gen_csd, net->gen_csd + G);
+  h->hg.u0.assign(net->gen_u0, net->gen_u0 + G);
+  std::vector<double> S;
+  cold_start(net, adm, *params, S);
+
+  h->arena_bytes = carve(h, nullptr);
+  if (hipMalloc(&h->arena, h->arena_bytes) != hipSuccess) {
+    const size_t bytes = h->arena_bytes;
+    delete h;
+    return fail(nullptr, UCAC_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+  }
+  carve(h, (char*)h->arena);
+  auto cleanup = [&](int code) {
+    g_create_error = h->err;
+    ucac_destroy(h);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "stream create failed"));
+  h->stream = h->own;
+  if (hipHostMalloc((void**)&h->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_sc, sizeof(double) * NSC, hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(h, UCAC_E_NOMEM, "pinned host allocation failed"));
+  if (hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
+
+  const Net& n = h->net;
+  struct Up { void* dst; const void* src; size_t bytes; } ups[] = {
+      {(void*)n.from, from.data(), sizeof(int) * L}, {(void*)n.to, to.data(), sizeof(int) * L},
+      {(void*)n.adm, adm.data(), sizeof(double) * 8 * L}, {(void*)n.rate, rate.data(), sizeof(double) * L},
+      {(void*)n.gs, net->bus_gs, sizeof(double) * N}, {(void*)n.bs, net->bus_bs, sizeof(double) * N},
+      {(void*)n.vmin, net->bus_vmin, sizeof(double) * N}, {(void*)n.vmax, net->bus_vmax, sizeof(double) * N},
+      {(void*)n.Pd, net->load_p, sizeof(double) * T * N}, {(void*)n.Qd, net->load_q, sizeof(double) * T * N},
+      {(void*)n.inc_start, inc_start.data(), sizeof(int) * (N + 1)}, {(void*)n.inc_code, inc_code.data(), sizeof(int) * 2 * L},
+      {(void*)n.gen_start, gen_start.data(), sizeof(int) * (N + 1)}, {(void*)n.gen_list, gen_list.data(), sizeof(int) * G},
+      {(void*)n.pmin, net->gen_pmin, sizeof(double) * G}, {(void*)n.pmax, net->gen_pmax, sizeof(double) * G},
+      {(void*)n.qmin, net->gen_qmin, sizeof(double) * G}, {(void*)n.qmax, net->gen_qmax, sizeof(double) * G},
+      {(void*)n.k2, h->hg.k2.data(), sizeof(double) * G}, {(void*)n.k1, h->hg.k1.data(), sizeof(double) * G},
+      {(void*)n.cnl, net->gen_cnl, sizeof(double) * G}, {(void*)n.csu, net->gen_csu, sizeof(double) * G},
+      {(void*)n.csd, net->gen_csd, sizeof(double) * G}, {(void*)n.ru, net->gen_ru, sizeof(double) * G},
+      {(void*)n.rd, net->gen_rd, sizeof(double) * G}, {(void*)n.su, net->gen_su, sizeof(double) * G},
+      {(void*)n.sd, net->gen_sd, sizeof(double) * G}, {(void*)n.p0, net->gen_p0, sizeof(double) * G},
+      {(void*)n.tu, net->gen_min_up, sizeof(int) * G}, {(void*)n.td, net->gen_min_dn, sizeof(int) * G},
+      {(void*)n.u0, net->gen_u0, sizeof(int) * G}, {(void*)n.lon, net->gen_init_on, sizeof(int) * G},
+      {(void*)n.loff, net->gen_init_off, sizeof(int) * G},
+      {(void*)h->d_state, S.data(), sizeof(double) * h->n_state}};
+  for (const Up& u : ups) {
+    if (u.bytes == 0) continue;
+    if (hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "upload failed"));
+  }
+  if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
+      hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
+      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 4) != hipSuccess)
+    return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
+  h->kp = kernel_params(*params);
+  if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "sync failed"));
+  if (build_graph(h) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
+  *out = h;
+  return UCAC_OK;
+}
+
+int ucac_set_stream(ucac_handle* h, void* hip_stream) {
+  if (!h) return UCAC_E_INVAL;
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  h->stream = hip_stream ? (hipStream_t)hip_stream : h->own;
+  return UCAC_OK;
+}
+
+static int check_bad(ucac_handle* h) {
+  if (h->h_ctl->bad) return fail(h, UCAC_E_NUMERIC, "non-finite residual in the iterate");
+  return UCAC_OK;
+}
+
+int ucac_step(ucac_handle* h, int32_t n_iters) {
+  if (!h) return UCAC_E_INVAL;
+  if (n_iters < 0) return fail(h, UCAC_E_INVAL, "negative iteration count");
+  HIP_OR(h, hipSetDevice(h->par.device));
+  int rc = set_ctl(h, 0, h->par.tol);
+  if (rc) return rc;
+  for (int i = 0; i < n_iters; ++i) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
+  rc = read_status(h);
+  if (rc) return rc;
+  return check_bad(h);
+}
+
+int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_done) {
+  if (!h) return UCAC_E_INVAL;
+  if (!(tol > 0.0) || max_iters < 0) return fail(h, UCAC_E_INVAL, "bad tol or max_iters");
+  HIP_OR(h, hipSetDevice(h->par.device));
+  h->par.tol = tol;
+  int rc = read_status(h);
+  if (rc) return rc;
+  const double it0 = h->h_sc[SC_ITER];
+  // clear the converged flag of a previous solve
+  h->h_sc[SC_CONV] = 0.0;
+  HIP_OR(h, hipMemcpyAsync(h->st.sc + SC_CONV, h->h_sc + SC_CONV, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  rc = set_ctl(h, 1, tol);
+  if (rc) return rc;
+  int launched = 0;
+  bool done = false;
+  while (!done && launched < max_iters) {
+    const int k = (max_iters - launched) < SOLVE_CHUNK ? (max_iters - launched) : SOLVE_CHUNK;
+    for (int i = 0; i < k; ++i) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
+    launched += k;
+    rc = read_status(h);
+    if (rc) return rc;
+    if (h->h_ctl->bad) break;
+    done = h->h_sc[SC_CONV] != 0.0;
+  }
+  rc = read_status(h);
+  if (rc) return rc;
+  if (iters_done) *iters_done = (int32_t)(h->h_sc[SC_ITER] - it0);
+  rc = check_bad(h);
+  if (rc) return rc;
+  return h->h_sc[SC_CONV] != 0.0 ? UCAC_OK : UCAC_NOT_CONVERGED;
+}
+
+int ucac_residuals(const ucac_handle* hc, double* r_primal, double* r_dual, double* z_inf, double* objective) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h) return UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  int rc = read_status(h);
+  if (rc) return rc;
+  if (r_primal) *r_primal = h->h_sc[SC_RP];
+  if (r_dual) *r_dual = h->h_sc[SC_RD];
+  if (z_inf) *z_inf = h->h_sc[SC_ZINF];
+  if (objective) {
+    const size_t TG = (size_t)h->T * h->G;
+    std::vector<double> buf(4 * TG);
+    if (TG) {
+      HIP_OR(h, hipMemcpy(buf.data(), h->st.p, sizeof(double) * TG, hipMemcpyDeviceToHost));
+      HIP_OR(h, hipMemcpy(buf.data() + TG, h->st.uon, sizeof(double) * 3 * TG, hipMemcpyDeviceToHost));
+    }
+    double obj = 0.0;
+    for (int t = 0; t < h->T; ++t)
+      for (int g = 0; g < h->G; ++g) {
+        const size_t k = (size_t)t * h->G + g;
+        const double p = buf[k];
+        obj += h->hg.k2[g] * p * p + h->hg.k1[g] * p;
+        obj += h->hg.cnl[g] * buf[TG + k] + h->hg.csu[g] * buf[2 * TG + k] + h->hg.csd[g] * buf[3 * TG + k];
+      }
+    *objective = obj;
+  }
+  return UCAC_OK;
+}
+
+int ucac_get_solution(const ucac_handle* hc, double* p, double* q, int8_t* u_on, int8_t* u_su, int8_t* u_sd, double* vm,
+                      double* va) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h) return UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  const size_t TG = (size_t)h->T * h->G, TN = (size_t)h->T * h->N;
+  if (p && TG) HIP_OR(h, hipMemcpy(p, h->st.p, sizeof(double) * TG, hipMemcpyDeviceToHost));
+  if (q && TG) HIP_OR(h, hipMemcpy(q, h->st.q, sizeof(double) * TG, hipMemcpyDeviceToHost));
+  double* uu[3] = {h->st.uon, h->st.usu, h->st.usd};
+  int8_t* uo[3] = {u_on, u_su, u_sd};
+  std::vector<double> tmp(TG > TN ? TG : TN);
+  for (int k = 0; k < 3; ++k) {
+    if (!uo[k] || !TG) continue;
+    HIP_OR(h, hipMemcpy(tmp.data(), uu[k], sizeof(double) * TG, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < TG; ++i) uo[k][i] = tmp[i] != 0.0 ? 1 : 0;
+  }
+  if (vm) {
+    HIP_OR(h, hipMemcpy(tmp.data(), h->st.wb, sizeof(double) * TN, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < TN; ++i) vm[i] = std::sqrt(std::fmax(tmp[i], 0.0));
+  }
+  if (va) HIP_OR(h, hipMemcpy(va, h->st.thb, sizeof(double) * TN, hipMemcpyDeviceToHost));
+  return UCAC_OK;
+}
+
+int ucac_get_state(const ucac_handle* hc, void* buf, size_t* bytes) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h || !bytes) return UCAC_E_INVAL;
+  const size_t need = sizeof(double) * h->n_state;
+  if (!buf) { *bytes = need; return UCAC_OK; }
+  if (*bytes < need) return fail(h, UCAC_E_STATE, "state buffer holds %zu bytes, %zu needed", *bytes, need);
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  HIP_OR(h, hipMemcpy(buf, h->d_state, need, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return UCAC_OK;
+}
+
+int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes) {
+  if (!h || !buf) return UCAC_E_INVAL;
+  const size_t need = sizeof(double) * h->n_state;
+  if (bytes != need) return fail(h, UCAC_E_STATE, "state of %zu bytes given, %zu expected", bytes, need);
+  const double* d = (const double*)buf;
+  // every entry finite except ||z^{k-1}||, which is +inf before the first outer update
+  for (size_t i = 0; i < h->n_state; ++i)
+    if (!std::isfinite(d[i]) && !(i == h->n_state - NSC + SC_ZPREV && d[i] == INFINITY))
+      return fail(h, UCAC_E_STATE, "state entry %zu is not finite", i);
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  HIP_OR(h, hipMemcpy(h->d_state, buf, need, hipMemcpyHostToDevice));
+  return set_ctl(h, 0, h->par.tol);
+}
+
+int ucac_get_branch_iters(const ucac_handle* hc, int32_t* iters) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h || !iters) return UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  const size_t TL = (size_t)h->T * h->L;
+  if (TL) HIP_OR(h, hipMemcpy(iters, h->st.br_iters, sizeof(int) * TL, hipMemcpyDeviceToHost));
+  return UCAC_OK;
+}
+
+int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots) {
+  if (!h || !avg_ms || n_iters < 1 || n_slots < UCAC_N_KERNELS) return h ? fail(h, UCAC_E_INVAL, "bad arguments") : UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  int rc = set_ctl(h, 0, h->par.tol);
+  if (rc) return rc;
+  const int K = UCAC_N_KERNELS;
+  std::vector<hipEvent_t> ev((size_t)n_iters * (K + 1), nullptr);
+  for (auto& e : ev) HIP_OR(h, hipEventCreate(&e));
+  hipError_t err = hipSuccess;
+  const char* where = "";
+  for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
+    hipEvent_t* e = &ev[(size_t)it * (K + 1)];
+    err = hipEventRecord(e[0], h->stream);
+    for (int k = 0; k < K && err == hipSuccess; ++k) {
+      err = launch_one(h, k, h->stream, &where);
+      if (err == hipSuccess) err = hipEventRecord(e[k + 1], h->stream);
+    }
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
+  for (int k = 0; k < K; ++k) avg_ms[k] = 0.0;
+  for (int it = 0; it < n_iters && err == hipSuccess; ++it)
+    for (int k = 0; k < K && err == hipSuccess; ++k) {
+      float ms = 0.0f;
+      err = hipEventElapsedTime(&ms, ev[(size_t)it * (K + 1) + k], ev[(size_t)it * (K + 1) + k + 1]);
+      avg_ms[k] += ms / n_iters;
+    }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(h, UCAC_E_DEVICE, "timed iteration failed at %s: %s", where, hipGetErrorString(err));
+  rc = read_status(h);
+  if (rc) return rc;
+  return check_bad(h);
+}
+
+int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset) {
+  if (!h || !out) return h ? fail(h, UCAC_E_INVAL, "null output") : UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  HIP_OR(h, hipMemcpy(out, h->st.br_count, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
+  if (reset) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 4));
+  return UCAC_OK;
+}
+
+const char* ucac_last_error(const ucac_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void ucac_destroy(ucac_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->par.device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
+  if (h->own) (void)hipStreamDestroy(h->own);
+  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->h_sc) (void)hipHostFree(h->h_sc);
+  if (h->arena) (void)hipFree(h->arena);
+  delete h;
+}
+
+}  // extern "C"

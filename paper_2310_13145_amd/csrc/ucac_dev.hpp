@@ -1,0 +1,117 @@
+// Internal device-side layout of the UC-ACOPF ADMM library (gfx950).
+//
+// Every per-(item, period) array is stored period-major, [t][item], so a
+// wavefront of consecutive lanes walks consecutive items of one period and every
+// SoA load/store of the generator, line and bus kernels is coalesced.  The
+// iterate lives in one flat FP64 buffer whose order is the state format of the
+// C-ABI (ucac_get_state); the kernels receive raw pointers into it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ucac {
+
+constexpr int NRB = 8;   // line rows: Pf Qf Pt Qt Wf Wt Thf Tht
+constexpr int NRG = 11;  // generator rows: G1 G2 C1..C6 U1 U2 U3
+enum { RB_PF, RB_QF, RB_PT, RB_QT, RB_WF, RB_WT, RB_TF, RB_TT };
+enum { RG_G1, RG_G2, RG_C1, RG_C2, RG_C3, RG_C4, RG_C5, RG_C6, RG_U1, RG_U2, RG_U3 };
+enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZINF, SC_CONV, NSC };
+enum { ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF, NACC };
+
+constexpr int BLOCK = 256;
+constexpr double TWO_PI = 6.283185307179586;
+
+// Device-resident control block of the iteration (never captured memsets: the
+// finalize kernel clears the accumulators after reading them).
+struct Ctl {
+  unsigned long long acc[NACC];  // max-reductions as the bit patterns of non-negative doubles
+  int halt;                      // set once converged in solve mode: every kernel returns at entry
+  int stop_at_tol;               // solve mode
+  int pending;                   // this iteration ended an inner loop: lambda kernel applies step:outer
+  int bad;                       // a NaN was seen in the residuals
+  double tol;
+  double beta_for_lambda;        // beta of the inner loop that just ended
+};
+
+struct Net {
+  int N, L, G, T, ref;
+  // lines [L]
+  const int* from;
+  const int* to;
+  const double* adm;  // [8][L]: G_ii B_ii G_ij B_ij G_jj B_jj G_ji B_ji
+  const double* rate;
+  // buses [N], loads [T][N]
+  const double *gs, *bs, *vmin, *vmax, *Pd, *Qd;
+  const int* inc_start;  // [N+1] incidence of line ends per bus
+  const int* inc_code;   // [2L] line*2 + side (0: from end, 1: to end)
+  const int* gen_start;  // [N+1]
+  const int* gen_list;   // [G]
+  // generators [G]
+  const double *pmin, *pmax, *qmin, *qmax, *k2, *k1, *cnl, *csu, *csd, *ru, *rd, *su, *sd, *p0;
+  const int *tu, *td, *u0, *lon, *loff;
+};
+
+struct State {
+  double *vf, *vt, *thf, *tht, *pf, *qf, *pt, *qt, *nuf, *nut;  // [T][L]
+  double *p, *q, *s;                                           // s: [6][T][G]
+  double *uon, *usu, *usd;                                     // [T][G] as 0.0 / 1.0
+  double *wb, *thb;                                            // [T][N]
+  double *Pbf, *Qbf, *Pbt, *Qbt;                               // [T][L]
+  double *pb, *qb, *ubon, *ubsu, *ubsd;                        // [T][G]
+  double *zB, *yB, *lB;                                        // [8][T][L]
+  double *zG, *yG, *lG;                                        // [11][T][G]
+  double* sc;                                                  // [NSC]
+  double* ub_nxt;                                              // [3][T][G] new relaxed commitments
+  int* br_iters;                                               // [T][L]
+  unsigned long long* br_count;                                // [4] running totals: evaluations, trial evaluations, CG its, Newton its
+  Ctl* ctl;
+};
+
+struct Par {
+  double rho_pq, rho_va, rho_uc, rho_cpl, mu;
+  double gtol;  // absolute projected-gradient tolerance
+  double tau, theta, lambda_max, beta_max, eps_in0;
+  int newton_max_iter, max_inner, warm_start;
+};
+
+// ---- reductions -------------------------------------------------------------
+
+// max that keeps a NaN visible (fmax alone would drop it)
+__device__ inline double nmax(double a, double b) { return (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000LL) : fmax(a, b); }
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = nmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide max of NV non-negative values, then one atomicMax per value.  The
+// IEEE bit patterns of non-negative doubles order like the values and a NaN
+// pattern exceeds every finite one, so the result is exact and independent of
+// the order in which blocks arrive.
+template <int NV>
+__device__ inline void block_max_to_ctl(const double (&v)[NV], const int (&slot)[NV], Ctl* ctl) {
+  __shared__ double red[NV][BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double w[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) w[k] = wave_max(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = w[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double m = red[k][0];
+      for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = nmax(m, red[k][i]);
+      atomicMax(&ctl->acc[slot[k]], (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+__device__ inline double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+}  // namespace ucac

@@ -1,0 +1,301 @@
+"""ctypes binding of the HIP library behind include/ucac.h.
+
+Argument marshalling only: every step of the iteration runs in the library's HIP
+kernels.  The functions keep the C names (ucac_create, ucac_step, ...); `Solver`
+is a small convenience wrapper around one handle.  PyTorch, when present, only
+supplies the HIP stream (``Solver.use_torch_stream``).
+
+Importing this module never builds anything; if the shared library is missing
+it raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libucac.so")
+
+UCAC_OK, UCAC_NOT_CONVERGED = 0, 1
+UCAC_E_INVAL, UCAC_E_NOMEM, UCAC_E_DEVICE, UCAC_E_STATE, UCAC_E_NUMERIC = -1, -2, -3, -4, -5
+
+
+class UcacError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ucac error {code}: {msg}")
+        self.code = code
+
+
+class ucac_network(C.Structure):
+    _fields_ = [
+        ("n_bus", C.c_int32), ("n_line", C.c_int32), ("n_gen", C.c_int32), ("T", C.c_int32),
+        ("ref_bus", C.c_int32), ("base_mva", C.c_double),
+        ("line_from", C.c_void_p), ("line_to", C.c_void_p),
+        ("line_r", C.c_void_p), ("line_x", C.c_void_p), ("line_b", C.c_void_p), ("line_rate", C.c_void_p),
+        ("bus_gs", C.c_void_p), ("bus_bs", C.c_void_p), ("bus_vmin", C.c_void_p), ("bus_vmax", C.c_void_p),
+        ("load_p", C.c_void_p), ("load_q", C.c_void_p),
+        ("gen_bus", C.c_void_p),
+        ("gen_pmin", C.c_void_p), ("gen_pmax", C.c_void_p), ("gen_qmin", C.c_void_p), ("gen_qmax", C.c_void_p),
+        ("gen_c2", C.c_void_p), ("gen_c1", C.c_void_p),
+        ("gen_cnl", C.c_void_p), ("gen_csu", C.c_void_p), ("gen_csd", C.c_void_p),
+        ("gen_ru", C.c_void_p), ("gen_rd", C.c_void_p), ("gen_su", C.c_void_p), ("gen_sd", C.c_void_p),
+        ("gen_min_up", C.c_void_p), ("gen_min_dn", C.c_void_p), ("gen_u0", C.c_void_p),
+        ("gen_init_on", C.c_void_p), ("gen_init_off", C.c_void_p),
+        ("gen_p0", C.c_void_p),
+    ]
+
+
+class ucac_params(C.Structure):
+    _fields_ = [
+        ("rho_pq", C.c_double), ("rho_va", C.c_double), ("rho_uc", C.c_double), ("rho_cpl", C.c_double),
+        ("beta0", C.c_double), ("tau", C.c_double), ("theta", C.c_double), ("lambda_max", C.c_double),
+        ("beta_max", C.c_double), ("mu_line", C.c_double),
+        ("newton_max_iter", C.c_int32), ("newton_gtol", C.c_double),
+        ("max_inner", C.c_int32), ("eps_in0", C.c_double), ("tol", C.c_double),
+        ("warm_start", C.c_int32), ("device", C.c_int32),
+    ]
+
+
+_INT_FIELDS = {"line_from", "line_to", "gen_bus", "gen_min_up", "gen_min_dn", "gen_u0", "gen_init_on", "gen_init_off"}
+
+_lib = None
+
+
+def lib():
+    """Load libucac.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip = C.c_void_p, C.POINTER(C.c_int32)
+        dp = C.POINTER(C.c_double)
+        L.ucac_params_default.argtypes = [C.POINTER(ucac_params)]
+        L.ucac_params_default.restype = None
+        L.ucac_create.argtypes = [C.POINTER(ucac_network), C.POINTER(ucac_params), C.POINTER(vp)]
+        L.ucac_set_stream.argtypes = [vp, vp]
+        L.ucac_step.argtypes = [vp, C.c_int32]
+        L.ucac_solve.argtypes = [vp, C.c_double, C.c_int32, ip]
+        L.ucac_residuals.argtypes = [vp, dp, dp, dp, dp]
+        L.ucac_get_solution.argtypes = [vp] * 8
+        L.ucac_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.ucac_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.ucac_get_branch_iters.argtypes = [vp, vp]
+        L.ucac_last_error.argtypes = [vp]
+        L.ucac_last_error.restype = C.c_char_p
+        L.ucac_destroy.argtypes = [vp]
+        L.ucac_destroy.restype = None
+        L.ucac_kernel_times.argtypes = [vp, C.c_int32, vp, C.c_int32]
+        L.ucac_branch_counters.argtypes = [vp, vp, C.c_int32]
+        for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
+                     "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
+                     "ucac_kernel_times", "ucac_branch_counters"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def ucac_params_default(**over) -> ucac_params:
+    p = ucac_params()
+    lib().ucac_params_default(C.byref(p))
+    for k, v in over.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def make_network(inst):
+    """ucac_network view of an instance dict; returns (struct, keep-alive arrays)."""
+    net = ucac_network()
+    keep = []
+    for name, _ in ucac_network._fields_:
+        v = inst[name]
+        if name in ("n_bus", "n_line", "n_gen", "T", "ref_bus", "base_mva"):
+            setattr(net, name, v)
+            continue
+        a = np.ascontiguousarray(v, dtype=np.int32 if name in _INT_FIELDS else np.float64)
+        keep.append(a)
+        setattr(net, name, a.ctypes.data if a.size else None)
+    return net, keep
+
+
+NRB, NRG = 8, 11
+SCALARS = ("beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r_d", "z_inf", "converged")
+
+
+def state_layout(n_bus, n_line, n_gen, T):
+    """(name, count) pairs of the flat FP64 state of ucac_get_state, in order."""
+    TL, TG, TN = T * n_line, T * n_gen, T * n_bus
+    out = [(k, TL) for k in ("vf", "vt", "thf", "tht", "pf", "qf", "pt", "qt", "nuf", "nut")]
+    out += [(k, TG) for k in ("p", "q", "s1", "s2", "s3", "s4", "s5", "s6", "uon", "usu", "usd")]
+    out += [(k, TN) for k in ("wb", "thb")]
+    out += [(k, TL) for k in ("Pbf", "Qbf", "Pbt", "Qbt")]
+    out += [(k, TG) for k in ("pb", "qb", "ubon", "ubsu", "ubsd")]
+    for kind in ("zB", "yB", "lB"):
+        out += [(f"{kind}{r}", TL) for r in range(NRB)]
+    for kind in ("zG", "yG", "lG"):
+        out += [(f"{kind}{r}", TG) for r in range(NRG)]
+    out.append(("scalars", len(SCALARS)))
+    return out
+
+
+def split_state(flat, n_bus, n_line, n_gen, T):
+    """Named views of a flat state."""
+    out, off = {}, 0
+    for name, n in state_layout(n_bus, n_line, n_gen, T):
+        out[name] = flat[off:off + n]
+        off += n
+    if off != len(flat):
+        raise ValueError("state size does not match the instance dimensions")
+    sc = out.pop("scalars")
+    for i, k in enumerate(SCALARS):
+        out[k] = float(sc[i])
+    return out
+
+
+def ucac_last_error(h=None) -> str:
+    s = lib().ucac_last_error(h)
+    return s.decode() if s else ""
+
+
+def _check(rc, h=None, ok=(UCAC_OK,)):
+    if rc not in ok:
+        raise UcacError(rc, ucac_last_error(h))
+    return rc
+
+
+def ucac_create(inst, params: ucac_params):
+    net, keep = make_network(inst)
+    h = C.c_void_p()
+    rc = lib().ucac_create(C.byref(net), C.byref(params), C.byref(h))
+    _check(rc, None)
+    return h
+
+
+def ucac_set_stream(h, stream_ptr):
+    return _check(lib().ucac_set_stream(h, C.c_void_p(stream_ptr) if stream_ptr else None), h)
+
+
+def ucac_step(h, n_iters):
+    return _check(lib().ucac_step(h, int(n_iters)), h)
+
+
+def ucac_solve(h, tol, max_iters):
+    it = C.c_int32(0)
+    rc = _check(lib().ucac_solve(h, float(tol), int(max_iters), C.byref(it)), h, ok=(UCAC_OK, UCAC_NOT_CONVERGED))
+    return rc, it.value
+
+
+def ucac_residuals(h):
+    out = [C.c_double() for _ in range(4)]
+    _check(lib().ucac_residuals(h, *[C.byref(o) for o in out]), h)
+    return tuple(o.value for o in out)
+
+
+def ucac_get_solution(h, n_bus, n_gen, T):
+    p = np.empty((T, n_gen)); q = np.empty((T, n_gen))
+    u = [np.empty((T, n_gen), np.int8) for _ in range(3)]
+    vm = np.empty((T, n_bus)); va = np.empty((T, n_bus))
+    _check(lib().ucac_get_solution(h, _ptr(p), _ptr(q), _ptr(u[0]), _ptr(u[1]), _ptr(u[2]), _ptr(vm), _ptr(va)), h)
+    return dict(p=p, q=q, u_on=u[0], u_su=u[1], u_sd=u[2], vm=vm, va=va)
+
+
+def ucac_get_state(h):
+    n = C.c_size_t(0)
+    _check(lib().ucac_get_state(h, None, C.byref(n)), h)
+    buf = np.empty(n.value // 8, dtype=np.float64)
+    _check(lib().ucac_get_state(h, _ptr(buf), C.byref(n)), h)
+    return buf
+
+
+def ucac_set_state(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.float64)
+    return _check(lib().ucac_set_state(h, _ptr(buf), buf.nbytes), h)
+
+
+def ucac_get_branch_iters(h, n_line, T):
+    out = np.empty(T * n_line, dtype=np.int32)
+    _check(lib().ucac_get_branch_iters(h, _ptr(out)), h)
+    return out
+
+
+KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda")
+
+
+def ucac_kernel_times(h, n_iters):
+    """n_iters iterations launched kernel by kernel with HIP events; mean ms per kernel."""
+    out = np.zeros(len(KERNELS))
+    _check(lib().ucac_kernel_times(h, int(n_iters), _ptr(out), len(KERNELS)), h)
+    return dict(zip(KERNELS, out.tolist()))
+
+
+def ucac_branch_counters(h, reset=False):
+    out = np.zeros(4, dtype=np.uint64)
+    _check(lib().ucac_branch_counters(h, _ptr(out), int(bool(reset))), h)
+    return dict(evals=int(out[0]), trials=int(out[1]), cg=int(out[2]), newton=int(out[3]))
+
+
+def ucac_destroy(h):
+    if h:
+        lib().ucac_destroy(h)
+
+
+class Solver:
+    """One UC-ACOPF instance resident on the GPU."""
+
+    def __init__(self, inst, params: ucac_params | None = None, **over):
+        self.inst = inst
+        self.params = params if params is not None else ucac_params_default(**over)
+        self.dims = (inst["n_bus"], inst["n_line"], inst["n_gen"], inst["T"])
+        self.h = ucac_create(inst, self.params)
+
+    def close(self):
+        if getattr(self, "h", None):
+            ucac_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def use_torch_stream(self):
+        import torch
+        ucac_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def step(self, n=1):
+        ucac_step(self.h, n)
+
+    def solve(self, tol=1e-4, max_iters=20000):
+        return ucac_solve(self.h, tol, max_iters)
+
+    def residuals(self):
+        return ucac_residuals(self.h)
+
+    def solution(self):
+        N, L, G, T = self.dims
+        return ucac_get_solution(self.h, N, G, T)
+
+    def get_state(self):
+        return ucac_get_state(self.h)
+
+    def set_state(self, buf):
+        ucac_set_state(self.h, buf)
+
+    def kernel_times(self, n_iters):
+        return ucac_kernel_times(self.h, n_iters)
+
+    def branch_counters(self, reset=False):
+        return ucac_branch_counters(self.h, reset)
+
+    def branch_iters(self):
+        N, L, G, T = self.dims
+        return ucac_get_branch_iters(self.h, L, T)
