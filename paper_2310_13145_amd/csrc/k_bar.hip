@@ -116,10 +116,35 @@ __device__ inline void zy_update(double* zr, double* yr, const double* lr, int k
   zinf = nmax(zinf, fabs(z));
 }
 
+// Line ends of a bus are visited in groups of GROUP with predicated (clamped)
+// loads, so each group's gathers are issued together as straight-line code: the
+// kernel is bound by gather latency, and this gives every lane GROUP loads in
+// flight instead of one dependent chain per line end.
+constexpr int GROUP = 4;
+
+struct EndData {
+  int k, rP, rQ, rW, rT;
+  double fP, fQ, v, th, tP, tQ;
+};
+
+__device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, int code, double rpq) {
+  EndData d;
+  const int l = code >> 1, side = code & 1;
+  d.k = t * n.L + l;
+  d.rP = side ? RB_PT : RB_PF; d.rQ = side ? RB_QT : RB_QF; d.rW = side ? RB_WT : RB_WF; d.rT = side ? RB_TT : RB_TF;
+  d.fP = side ? s.pt[d.k] : s.pf[d.k];
+  d.fQ = side ? s.qt[d.k] : s.qf[d.k];
+  d.v = side ? s.vt[d.k] : s.vf[d.k];
+  d.th = side ? s.tht[d.k] : s.thf[d.k];
+  d.tP = d.fP + s.zB[d.rP * TL + d.k] + s.yB[d.rP * TL + d.k] / rpq;
+  d.tQ = d.fQ + s.zB[d.rQ * TL + d.k] + s.yB[d.rQ * TL + d.k] / rpq;
+  return d;
+}
+
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) {
   if (s.ctl->halt) return;
-  const int N = n.N, L = n.L, G = n.G, T = n.T;
-  const int TL = T * L, TG = T * G;
+  const int N = n.N, G = n.G, T = n.T;
+  const int TL = T * n.L, TG = T * G;
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
@@ -129,20 +154,33 @@ __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) {
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const int code = n.inc_code[e], l = code >> 1, side = code & 1;
-      const int k = t * L + l;
-      const int rP = side ? RB_PT : RB_PF, rQ = side ? RB_QT : RB_QF, rW = side ? RB_WT : RB_WF, rT = side ? RB_TT : RB_TF;
-      const double fP = side ? s.pt[k] : s.pf[k], fQ = side ? s.qt[k] : s.qf[k];
-      const double v = side ? s.vt[k] : s.vf[k], th = side ? s.tht[k] : s.thf[k];
-      M11 += 1.0 / rpq;
-      aT -= fP + s.zB[rP * TL + k] + s.yB[rP * TL + k] / rpq;
-      M22 += 1.0 / rpq;
-      bT -= fQ + s.zB[rQ * TL + k] + s.yB[rQ * TL + k] / rpq;
-      Ww += rva;
-      Sw += rva * (v * v + s.zB[rW * TL + k] + s.yB[rW * TL + k] / rva);
-      Wt += rva;
-      St += rva * (th + s.zB[rT * TL + k] + s.yB[rT * TL + k] / rva);
+    for (int e = e0; e < e1; e += GROUP) {
+      int code[GROUP];
+      double on[GROUP];
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) {
+        const bool in = e + j < e1;
+        code[j] = n.inc_code[in ? e + j : e0];
+        on[j] = in ? 1.0 : 0.0;
+      }
+      EndData d[GROUP];
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) d[j] = load_end(n, s, t, TL, code[j], rpq);
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) {
+        const double zW = s.zB[d[j].rW * TL + d[j].k], yW = s.yB[d[j].rW * TL + d[j].k];
+        const double zT = s.zB[d[j].rT * TL + d[j].k], yT = s.yB[d[j].rT * TL + d[j].k];
+        if (on[j] != 0.0) {
+          M11 += 1.0 / rpq;
+          aT -= d[j].tP;
+          M22 += 1.0 / rpq;
+          bT -= d[j].tQ;
+          Ww += rva;
+          Sw += rva * (d[j].v * d[j].v + zW + yW / rva);
+          Wt += rva;
+          St += rva * (d[j].th + zT + yT / rva);
+        }
+      }
     }
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
     for (int e = g0; e < g1; ++e) {
@@ -179,24 +217,39 @@ __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) {
     s.wb[idx] = wnew;
     s.thb[idx] = thnew;
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
-    for (int e = e0; e < e1; ++e) {
-      const int code = n.inc_code[e], l = code >> 1, side = code & 1;
-      const int k = t * L + l;
-      const int rP = side ? RB_PT : RB_PF, rQ = side ? RB_QT : RB_QF, rW = side ? RB_WT : RB_WF, rT = side ? RB_TT : RB_TF;
-      const double fP = side ? s.pt[k] : s.pf[k], fQ = side ? s.qt[k] : s.qf[k];
-      const double v = side ? s.vt[k] : s.vf[k], th = side ? s.tht[k] : s.thf[k];
-      const double tP = fP + s.zB[rP * TL + k] + s.yB[rP * TL + k] / rpq;
-      const double tQ = fQ + s.zB[rQ * TL + k] + s.yB[rQ * TL + k] / rpq;
-      const double Pn = tP - mu1 / rpq, Qn = tQ - mu2 / rpq;
-      double* Pdup = side ? s.Pbt : s.Pbf;
-      double* Qdup = side ? s.Qbt : s.Qbf;
-      rd = nmax(rd, nmax(fabs(Pn - Pdup[k]), fabs(Qn - Qdup[k])));
-      Pdup[k] = Pn;
-      Qdup[k] = Qn;
-      zy_update(s.zB + rP * TL, s.yB + rP * TL, s.lB + rP * TL, k, fP - Pn, rpq, beta, rp, rin, zinf);
-      zy_update(s.zB + rQ * TL, s.yB + rQ * TL, s.lB + rQ * TL, k, fQ - Qn, rpq, beta, rp, rin, zinf);
-      zy_update(s.zB + rW * TL, s.yB + rW * TL, s.lB + rW * TL, k, v * v - wnew, rva, beta, rp, rin, zinf);
-      zy_update(s.zB + rT * TL, s.yB + rT * TL, s.lB + rT * TL, k, th - thnew, rva, beta, rp, rin, zinf);
+    for (int e = e0; e < e1; e += GROUP) {
+      int code[GROUP];
+      bool on[GROUP];
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) {
+        on[j] = e + j < e1;
+        code[j] = n.inc_code[on[j] ? e + j : e0];
+      }
+      EndData d[GROUP];
+      double Pold[GROUP], Qold[GROUP];
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) {
+        d[j] = load_end(n, s, t, TL, code[j], rpq);
+        const bool side = code[j] & 1;
+        Pold[j] = side ? s.Pbt[d[j].k] : s.Pbf[d[j].k];
+        Qold[j] = side ? s.Qbt[d[j].k] : s.Qbf[d[j].k];
+      }
+#pragma unroll
+      for (int j = 0; j < GROUP; ++j) {
+        if (!on[j]) continue;
+        const bool side = code[j] & 1;
+        const int k = d[j].k;
+        const double Pn = d[j].tP - mu1 / rpq, Qn = d[j].tQ - mu2 / rpq;
+        double* Pdup = side ? s.Pbt : s.Pbf;
+        double* Qdup = side ? s.Qbt : s.Qbf;
+        rd = nmax(rd, nmax(fabs(Pn - Pold[j]), fabs(Qn - Qold[j])));
+        Pdup[k] = Pn;
+        Qdup[k] = Qn;
+        zy_update(s.zB + d[j].rP * TL, s.yB + d[j].rP * TL, s.lB + d[j].rP * TL, k, d[j].fP - Pn, rpq, beta, rp, rin, zinf);
+        zy_update(s.zB + d[j].rQ * TL, s.yB + d[j].rQ * TL, s.lB + d[j].rQ * TL, k, d[j].fQ - Qn, rpq, beta, rp, rin, zinf);
+        zy_update(s.zB + d[j].rW * TL, s.yB + d[j].rW * TL, s.lB + d[j].rW * TL, k, d[j].v * d[j].v - wnew, rva, beta, rp, rin, zinf);
+        zy_update(s.zB + d[j].rT * TL, s.yB + d[j].rT * TL, s.lB + d[j].rT * TL, k, d[j].th - thnew, rva, beta, rp, rin, zinf);
+      }
     }
     for (int e = g0; e < g1; ++e) {
       const int g = n.gen_list[e], k = t * G + g;

@@ -2,7 +2,9 @@
 // cold start, the captured iteration graph and the control loop of ucac_solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -47,6 +49,8 @@ struct ucac_handle {
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
+  // locality ordering: internal index -> caller's index
+  std::vector<int> perm_bus, perm_line, perm_gen;
   std::string err;
 };
 
@@ -260,6 +264,134 @@ void cold_start(const ucac_network* n, const std::vector<double>& adm, const uca
   sc[SC_ZPREV] = INFINITY;
 }
 
+// ---- locality ordering ------------------------------------------------------
+//
+// The bus kernel gathers the x-side values of every incident line end and the line
+// kernel gathers the duplicates of both end buses.  With the caller's numbering,
+// consecutive lanes touch unrelated lines, so nearly every gather fetches a whole
+// cache line for 8 useful bytes.  The library therefore renumbers buses by reverse
+// Cuthill-McKee (neighbours get near indices), lines by their lower-numbered end,
+// and units by their bus.  Everything the caller sees (state, solution, iteration
+// counts) is converted back at the boundary.
+
+void rcm_order(int N, const std::vector<std::vector<int>>& adj, std::vector<int>& order) {
+  std::vector<int> idx(N);
+  std::iota(idx.begin(), idx.end(), 0);
+  auto by_deg = [&](int a, int b) { return adj[a].size() != adj[b].size() ? adj[a].size() < adj[b].size() : a < b; };
+  std::stable_sort(idx.begin(), idx.end(), by_deg);
+  std::vector<char> seen(N, 0);
+  order.clear();
+  order.reserve(N);
+  for (int s0 : idx) {
+    if (seen[s0]) continue;
+    size_t head = order.size();
+    order.push_back(s0);
+    seen[s0] = 1;
+    for (; head < order.size(); ++head) {
+      std::vector<int> nb = adj[order[head]];
+      std::stable_sort(nb.begin(), nb.end(), by_deg);
+      for (int v : nb)
+        if (!seen[v]) { seen[v] = 1; order.push_back(v); }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+}
+
+struct Permuted {
+  ucac_network view;
+  std::vector<int32_t> from, to, gbus, tu, td, u0, lon, loff;
+  std::vector<double> r, x, b, rate, gs, bs, vmin, vmax, lp, lq;
+  std::vector<double> pmin, pmax, qmin, qmax, c2, c1, cnl, csu, csd, ru, rd, su, sd, p0;
+};
+
+void make_order(const ucac_network* n, std::vector<int>& pb, std::vector<int>& pl, std::vector<int>& pg) {
+  const int N = n->n_bus, L = n->n_line, G = n->n_gen;
+  std::vector<std::vector<int>> adj(N);
+  for (int l = 0; l < L; ++l) { adj[n->line_from[l]].push_back(n->line_to[l]); adj[n->line_to[l]].push_back(n->line_from[l]); }
+  rcm_order(N, adj, pb);
+  std::vector<int> inv(N);
+  for (int i = 0; i < N; ++i) inv[pb[i]] = i;
+  pl.resize(L);
+  std::iota(pl.begin(), pl.end(), 0);
+  std::stable_sort(pl.begin(), pl.end(), [&](int a, int c) {
+    const int a0 = std::min(inv[n->line_from[a]], inv[n->line_to[a]]), c0 = std::min(inv[n->line_from[c]], inv[n->line_to[c]]);
+    if (a0 != c0) return a0 < c0;
+    return std::max(inv[n->line_from[a]], inv[n->line_to[a]]) < std::max(inv[n->line_from[c]], inv[n->line_to[c]]);
+  });
+  pg.resize(G);
+  std::iota(pg.begin(), pg.end(), 0);
+  std::stable_sort(pg.begin(), pg.end(), [&](int a, int c) { return inv[n->gen_bus[a]] < inv[n->gen_bus[c]]; });
+}
+
+void permute_network(const ucac_network* n, const std::vector<int>& pb, const std::vector<int>& pl,
+                     const std::vector<int>& pg, Permuted& P) {
+  const int N = n->n_bus, L = n->n_line, G = n->n_gen, T = n->T;
+  std::vector<int> inv(N);
+  for (int i = 0; i < N; ++i) inv[pb[i]] = i;
+  auto bybus = [&](const double* a, std::vector<double>& out) { out.resize(N); for (int i = 0; i < N; ++i) out[i] = a[pb[i]]; };
+  auto byline = [&](const double* a, std::vector<double>& out) { out.resize(L); for (int l = 0; l < L; ++l) out[l] = a[pl[l]]; };
+  auto bygen = [&](const double* a, std::vector<double>& out) { out.resize(G); for (int g = 0; g < G; ++g) out[g] = a[pg[g]]; };
+  auto bygeni = [&](const int32_t* a, std::vector<int32_t>& out) { out.resize(G); for (int g = 0; g < G; ++g) out[g] = a[pg[g]]; };
+  P.from.resize(L); P.to.resize(L);
+  for (int l = 0; l < L; ++l) { P.from[l] = inv[n->line_from[pl[l]]]; P.to[l] = inv[n->line_to[pl[l]]]; }
+  byline(n->line_r, P.r); byline(n->line_x, P.x); byline(n->line_b, P.b); byline(n->line_rate, P.rate);
+  bybus(n->bus_gs, P.gs); bybus(n->bus_bs, P.bs); bybus(n->bus_vmin, P.vmin); bybus(n->bus_vmax, P.vmax);
+  P.lp.resize((size_t)T * N); P.lq.resize((size_t)T * N);
+  for (int t = 0; t < T; ++t)
+    for (int i = 0; i < N; ++i) { P.lp[(size_t)t * N + i] = n->load_p[(size_t)t * N + pb[i]]; P.lq[(size_t)t * N + i] = n->load_q[(size_t)t * N + pb[i]]; }
+  P.gbus.resize(G);
+  for (int g = 0; g < G; ++g) P.gbus[g] = inv[n->gen_bus[pg[g]]];
+  bygen(n->gen_pmin, P.pmin); bygen(n->gen_pmax, P.pmax); bygen(n->gen_qmin, P.qmin); bygen(n->gen_qmax, P.qmax);
+  bygen(n->gen_c2, P.c2); bygen(n->gen_c1, P.c1); bygen(n->gen_cnl, P.cnl); bygen(n->gen_csu, P.csu); bygen(n->gen_csd, P.csd);
+  bygen(n->gen_ru, P.ru); bygen(n->gen_rd, P.rd); bygen(n->gen_su, P.su); bygen(n->gen_sd, P.sd); bygen(n->gen_p0, P.p0);
+  bygeni(n->gen_min_up, P.tu); bygeni(n->gen_min_dn, P.td); bygeni(n->gen_u0, P.u0);
+  bygeni(n->gen_init_on, P.lon); bygeni(n->gen_init_off, P.loff);
+  ucac_network& v = P.view;
+  v = *n;
+  v.ref_bus = inv[n->ref_bus];
+  v.line_from = P.from.data(); v.line_to = P.to.data();
+  v.line_r = P.r.data(); v.line_x = P.x.data(); v.line_b = P.b.data(); v.line_rate = P.rate.data();
+  v.bus_gs = P.gs.data(); v.bus_bs = P.bs.data(); v.bus_vmin = P.vmin.data(); v.bus_vmax = P.vmax.data();
+  v.load_p = P.lp.data(); v.load_q = P.lq.data();
+  v.gen_bus = P.gbus.data();
+  v.gen_pmin = P.pmin.data(); v.gen_pmax = P.pmax.data(); v.gen_qmin = P.qmin.data(); v.gen_qmax = P.qmax.data();
+  v.gen_c2 = P.c2.data(); v.gen_c1 = P.c1.data(); v.gen_cnl = P.cnl.data(); v.gen_csu = P.csu.data(); v.gen_csd = P.csd.data();
+  v.gen_ru = P.ru.data(); v.gen_rd = P.rd.data(); v.gen_su = P.su.data(); v.gen_sd = P.sd.data(); v.gen_p0 = P.p0.data();
+  v.gen_min_up = P.tu.data(); v.gen_min_dn = P.td.data(); v.gen_u0 = P.u0.data();
+  v.gen_init_on = P.lon.data(); v.gen_init_off = P.loff.data();
+}
+
+// Convert a flat state between the caller's numbering and the internal one.
+void convert_state(const ucac_handle* h, const double* src, double* dst, bool to_internal) {
+  const size_t T = h->T;
+  struct Seg { const std::vector<int>* perm; int count; };
+  const Seg segs[] = {{&h->perm_line, 10}, {&h->perm_gen, 11}, {&h->perm_bus, 2}, {&h->perm_line, 4},
+                      {&h->perm_gen, 5}, {&h->perm_line, 3 * NRB}, {&h->perm_gen, 3 * NRG}};
+  size_t off = 0;
+  for (const Seg& sg : segs) {
+    const size_t n = sg.perm->size();
+    const int* pm = sg.perm->data();
+    for (int a = 0; a < sg.count; ++a) {
+      for (size_t t = 0; t < T; ++t) {
+        const double* sr = src + off + t * n;
+        double* ds = dst + off + t * n;
+        if (to_internal) for (size_t i = 0; i < n; ++i) ds[i] = sr[pm[i]];
+        else for (size_t i = 0; i < n; ++i) ds[pm[i]] = sr[i];
+      }
+      off += T * n;
+    }
+  }
+  for (int k = 0; k < NSC; ++k) dst[off + k] = src[off + k];
+}
+
+// [T][n] array from internal to caller numbering
+template <class V>
+void unpermute_rows(const std::vector<int>& perm, size_t T, const V* src, V* dst) {
+  const size_t n = perm.size();
+  for (size_t t = 0; t < T; ++t)
+    for (size_t i = 0; i < n; ++i) dst[t * n + perm[i]] = src[t * n + i];
+}
+
 Par kernel_params(const ucac_params& p) {
   Par k;
   k.rho_pq = p.rho_pq; k.rho_va = p.rho_va; k.rho_uc = p.rho_uc; k.rho_cpl = p.rho_cpl; k.mu = p.mu_line;
@@ -358,6 +490,10 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipSetDevice(params->device) != hipSuccess) return fail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed");
 
   ucac_handle* h = new ucac_handle();
+  Permuted perm;
+  make_order(net, h->perm_bus, h->perm_line, h->perm_gen);
+  permute_network(net, h->perm_bus, h->perm_line, h->perm_gen, perm);
+  net = &perm.view;
   h->N = net->n_bus; h->L = net->n_line; h->G = net->n_gen; h->T = net->T; h->ref = net->ref_bus;
   h->par = *params;
   const size_t N = h->N, L = h->L, G = h->G, T = h->T;
@@ -544,22 +680,32 @@ int ucac_get_solution(const ucac_handle* hc, double* p, double* q, int8_t* u_on,
   if (!h) return UCAC_E_INVAL;
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
-  const size_t TG = (size_t)h->T * h->G, TN = (size_t)h->T * h->N;
-  if (p && TG) HIP_OR(h, hipMemcpy(p, h->st.p, sizeof(double) * TG, hipMemcpyDeviceToHost));
-  if (q && TG) HIP_OR(h, hipMemcpy(q, h->st.q, sizeof(double) * TG, hipMemcpyDeviceToHost));
+  const size_t T = h->T, TG = T * h->G, TN = T * h->N;
+  std::vector<double> tmp(TG > TN ? TG : TN), out(TG > TN ? TG : TN);
+  double* dd[2] = {p, q};
+  double* ds[2] = {h->st.p, h->st.q};
+  for (int k = 0; k < 2; ++k) {
+    if (!dd[k] || !TG) continue;
+    HIP_OR(h, hipMemcpy(tmp.data(), ds[k], sizeof(double) * TG, hipMemcpyDeviceToHost));
+    unpermute_rows(h->perm_gen, T, tmp.data(), dd[k]);
+  }
   double* uu[3] = {h->st.uon, h->st.usu, h->st.usd};
   int8_t* uo[3] = {u_on, u_su, u_sd};
-  std::vector<double> tmp(TG > TN ? TG : TN);
   for (int k = 0; k < 3; ++k) {
     if (!uo[k] || !TG) continue;
     HIP_OR(h, hipMemcpy(tmp.data(), uu[k], sizeof(double) * TG, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < TG; ++i) uo[k][i] = tmp[i] != 0.0 ? 1 : 0;
+    unpermute_rows(h->perm_gen, T, tmp.data(), out.data());
+    for (size_t i = 0; i < TG; ++i) uo[k][i] = out[i] != 0.0 ? 1 : 0;
   }
   if (vm) {
     HIP_OR(h, hipMemcpy(tmp.data(), h->st.wb, sizeof(double) * TN, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < TN; ++i) vm[i] = std::sqrt(std::fmax(tmp[i], 0.0));
+    unpermute_rows(h->perm_bus, T, tmp.data(), out.data());
+    for (size_t i = 0; i < TN; ++i) vm[i] = std::sqrt(std::fmax(out[i], 0.0));
   }
-  if (va) HIP_OR(h, hipMemcpy(va, h->st.thb, sizeof(double) * TN, hipMemcpyDeviceToHost));
+  if (va) {
+    HIP_OR(h, hipMemcpy(tmp.data(), h->st.thb, sizeof(double) * TN, hipMemcpyDeviceToHost));
+    unpermute_rows(h->perm_bus, T, tmp.data(), va);
+  }
   return UCAC_OK;
 }
 
@@ -571,7 +717,9 @@ int ucac_get_state(const ucac_handle* hc, void* buf, size_t* bytes) {
   if (*bytes < need) return fail(h, UCAC_E_STATE, "state buffer holds %zu bytes, %zu needed", *bytes, need);
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
-  HIP_OR(h, hipMemcpy(buf, h->d_state, need, hipMemcpyDeviceToHost));
+  std::vector<double> tmp(h->n_state);
+  HIP_OR(h, hipMemcpy(tmp.data(), h->d_state, need, hipMemcpyDeviceToHost));
+  convert_state(h, tmp.data(), (double*)buf, false);
   *bytes = need;
   return UCAC_OK;
 }
@@ -587,7 +735,9 @@ int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes) {
       return fail(h, UCAC_E_STATE, "state entry %zu is not finite", i);
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
-  HIP_OR(h, hipMemcpy(h->d_state, buf, need, hipMemcpyHostToDevice));
+  std::vector<double> tmp(h->n_state);
+  convert_state(h, d, tmp.data(), true);
+  HIP_OR(h, hipMemcpy(h->d_state, tmp.data(), need, hipMemcpyHostToDevice));
   return set_ctl(h, 0, h->par.tol);
 }
 
@@ -597,7 +747,9 @@ int ucac_get_branch_iters(const ucac_handle* hc, int32_t* iters) {
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
   const size_t TL = (size_t)h->T * h->L;
-  if (TL) HIP_OR(h, hipMemcpy(iters, h->st.br_iters, sizeof(int) * TL, hipMemcpyDeviceToHost));
+  std::vector<int32_t> tmp(TL);
+  if (TL) HIP_OR(h, hipMemcpy(tmp.data(), h->st.br_iters, sizeof(int) * TL, hipMemcpyDeviceToHost));
+  unpermute_rows(h->perm_line, (size_t)h->T, tmp.data(), iters);
   return UCAC_OK;
 }
 

@@ -9,8 +9,8 @@ The paper's experiments use MATPOWER IEEE cases with an ISO-NE demand profile
 stand-in with the parameter distributions below:
 
 * topology: a ring plus chords (9-bus case) or a planar Delaunay mesh made
-  connected by its Euclidean minimum spanning tree and then filled with the
-  shortest remaining Delaunay edges up to the requested line count;
+  connected by its Euclidean minimum spanning tree and then filled with Delaunay
+  edges drawn uniformly at random up to the requested line count;
 * lines: r ~ U(0.005, 0.03), x ~ U(0.05, 0.2), b ~ U(0, 0.2), rating ~ U(1.5, 3) p.u.;
 * generators at distinct random buses: c2 ~ U(0.01, 0.1) $/MW^2h, c1 ~ U(10, 40) $/MWh,
   start-up cost ~ U(100, 500) $, Pmax ~ U(1, 3) p.u., Pmin = 0.2 Pmax,
@@ -75,7 +75,11 @@ def _delaunay_mesh(rng, n, n_line):
     chosen = {(min(a, b), max(a, b)) for a, b in zip(mst.row.tolist(), mst.col.tolist())}
     if len(chosen) != n - 1:
         raise RuntimeError("Delaunay graph is not connected")
-    for k in np.argsort(length, kind="stable"):
+    # the remaining lines are Delaunay edges drawn uniformly at random: adding the
+    # shortest ones instead only thickens dense clusters and leaves long tree-like
+    # corridors (a 2000-bus mesh then has diameter ~180 and a DC dispatch overloads
+    # ~190 lines by up to 5x); random edges give diameter ~50 and a loadable grid
+    for k in rng.permutation(len(cand)):
         if len(chosen) >= n_line:
             break
         chosen.add(cand[k])
