@@ -160,6 +160,11 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
  * zeroes them after reading. */
 int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
 
+/* After ucac_solve (or ucac_step): first_iter[m] (m = 0, 1, 2) receives the first
+ * iteration of that call at which both r_primal and r_dual were <= 1e-2, 1e-3,
+ * 1e-4 respectively, or -1 if never.  Recorded on the device every iteration. */
+int ucac_solve_milestones(const ucac_handle* h, int32_t* first_iter);
+
 /* Message of the last error on this handle (or of the last failed create when
  * h is NULL).  Valid until the next call on the handle. */
 const char* ucac_last_error(const ucac_handle* h);

@@ -28,6 +28,9 @@ __global__ void k_finalize(Net n, State s, Par p) {
   sc[SC_LIN] += 1.0;
   c->pending = 0;
   if (rp != rp || rin != rin || rd != rd || zinf != zinf) c->bad = 1;
+  c->ms_count += 1;
+  for (int m = 0; m < 3; ++m)
+    if (c->ms_iter[m] < 0 && rp <= c->ms_tol[m] && rd <= c->ms_tol[m]) c->ms_iter[m] = c->ms_count;
   if (c->stop_at_tol && rp <= c->tol && rd <= c->tol) {
     sc[SC_CONV] = 1.0;
     c->halt = 1;

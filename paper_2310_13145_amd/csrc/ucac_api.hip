@@ -455,6 +455,8 @@ int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
   std::memset(h->h_ctl, 0, sizeof(Ctl));
   h->h_ctl->stop_at_tol = stop_at_tol;
   h->h_ctl->tol = tol;
+  const double ms[3] = {1e-2, 1e-3, 1e-4};
+  for (int m = 0; m < 3; ++m) { h->h_ctl->ms_tol[m] = ms[m]; h->h_ctl->ms_iter[m] = -1; }
   HIP_OR(h, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   return UCAC_OK;
 }
@@ -792,6 +794,16 @@ int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset) {
   HIP_OR(h, hipStreamSynchronize(h->stream));
   HIP_OR(h, hipMemcpy(out, h->st.br_count, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
   if (reset) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 4));
+  return UCAC_OK;
+}
+
+int ucac_solve_milestones(const ucac_handle* hc, int32_t* first_iter) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h || !first_iter) return h ? fail(h, UCAC_E_INVAL, "null output") : UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  int rc = read_status(h);
+  if (rc) return rc;
+  for (int m = 0; m < 3; ++m) first_iter[m] = h->h_ctl->ms_iter[m];
   return UCAC_OK;
 }
 

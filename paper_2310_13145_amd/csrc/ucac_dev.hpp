@@ -32,6 +32,9 @@ struct Ctl {
   int bad;                       // a NaN was seen in the residuals
   double tol;
   double beta_for_lambda;        // beta of the inner loop that just ended
+  double ms_tol[3];              // residual milestones 1e-2, 1e-3, 1e-4 of a solve
+  int ms_iter[3];                // first iteration (counted from the solve start) with r_p, r_d <= ms_tol; -1 if not yet
+  int ms_count;                  // iterations since the solve started
 };
 
 struct Net {

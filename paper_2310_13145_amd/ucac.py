@@ -89,9 +89,10 @@ def lib():
         L.ucac_destroy.restype = None
         L.ucac_kernel_times.argtypes = [vp, C.c_int32, vp, C.c_int32]
         L.ucac_branch_counters.argtypes = [vp, vp, C.c_int32]
+        L.ucac_solve_milestones.argtypes = [vp, vp]
         for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
                      "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
-                     "ucac_kernel_times", "ucac_branch_counters"):
+                     "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -242,6 +243,13 @@ def ucac_branch_counters(h, reset=False):
     return dict(evals=int(out[0]), trials=int(out[1]), cg=int(out[2]), newton=int(out[3]))
 
 
+def ucac_solve_milestones(h):
+    """First iteration of the last solve/step call with r_p, r_d <= 1e-2, 1e-3, 1e-4 (-1: never)."""
+    out = np.zeros(3, dtype=np.int32)
+    _check(lib().ucac_solve_milestones(h, _ptr(out)), h)
+    return {"1e-2": int(out[0]), "1e-3": int(out[1]), "1e-4": int(out[2])}
+
+
 def ucac_destroy(h):
     if h:
         lib().ucac_destroy(h)
@@ -289,6 +297,9 @@ class Solver:
 
     def set_state(self, buf):
         ucac_set_state(self.h, buf)
+
+    def milestones(self):
+        return ucac_solve_milestones(self.h)
 
     def kernel_times(self, n_iters):
         return ucac_kernel_times(self.h, n_iters)
