@@ -156,14 +156,62 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
 
 /* Running totals of the line kernel's work since create or the last reset:
  * out[0] full evaluations (value, gradient, Hessian), out[1] trial evaluations
- * (value only), out[2] CG iterations, out[3] Newton iterations.  reset != 0
- * zeroes them after reading. */
+ * (value only), out[2] CG iterations, out[3] Newton iterations, out[4] learned
+ * starts that fell back to the flat start (out has 5 slots).  reset != 0 zeroes
+ * them after reading. */
 int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
 
 /* After ucac_solve (or ucac_step): first_iter[m] (m = 0, 1, 2) receives the first
  * iteration of that call at which both r_primal and r_dual were <= 1e-2, 1e-3,
  * 1e-4 respectively, or -1 if never.  Recorded on the device every iteration. */
 int ucac_solve_milestones(const ucac_handle* h, int32_t* first_iter);
+
+/* ---- learned warm start of the line Newton solves --------------------------
+ * A 20 -> 64 -> 64 -> 4 perceptron with SiLU activations, BF16 weights and FP32
+ * accumulation on the matrix cores, predicts each line subproblem's solution
+ * from its local data; Newton starts there, and a lane that does not reach the
+ * Newton tolerance restarts from the flat start (the plain method stays the
+ * fallback and judge; the tolerance is unchanged).  Parameters are one FP32
+ * vector of UCAC_MLP_PARAMS values: W1 [64][20], b1 [64], W2 [64][64], b2 [64],
+ * W3 [4][64], b3 [4] (row-major).  Inputs per line and period (20): 0.1 G_ii,
+ * 0.05 B_ij, 10 (B_ii + B_ij), rating/3, the four flow targets, the two
+ * voltage-square targets minus 1, 5 (angle target difference), the two
+ * line-limit multipliers / mu, the four voltage bounds minus 1, log10(rho_pq) - 4,
+ * log10(rho_va) - 4, (target P^2 + Q^2 - rating^2) / rating^2 at the from end.
+ * Outputs (4): v_i - 1, v_j - 1, 10 (th_i - angle target i), 10 (th_j - target j). */
+#define UCAC_MLP_PARAMS 5764
+
+/* Load trained weights into the handle and use the learned start from the next
+ * iteration on (the warm_start mode becomes 2).  weights == NULL returns to the
+ * start of ucac_params.warm_start.  UCAC_E_INVAL for a wrong count or NaN/Inf. */
+int ucac_set_warmstart(ucac_handle* h, const float* weights, size_t n);
+
+/* Training data from the method itself: run n_iters inner iterations (as
+ * ucac_step) and, in iteration i, log every stride-th line solve starting at
+ * offset i % stride: its 20 inputs and its converged solution in the 4-output
+ * encoding, into caller arrays feats [cap][20] and targets [cap][4] (host).
+ * *n_logged receives the number of pairs kept (at most cap). */
+int ucac_log_pairs(ucac_handle* h, int32_t n_iters, int32_t stride, float* feats, float* targets, int64_t cap,
+                   int64_t* n_logged);
+
+typedef struct ucac_mlp ucac_mlp;
+
+/* A network on device `device`, weights drawn from U(-1/sqrt(fan_in), +) with
+ * this seed, zero biases. */
+int ucac_mlp_create(int32_t device, uint64_t seed, ucac_mlp** out);
+int ucac_mlp_set_weights(ucac_mlp* m, const float* weights, size_t n);   /* n == UCAC_MLP_PARAMS; resets Adam */
+int ucac_mlp_get_weights(const ucac_mlp* m, float* weights, size_t n);
+/* y [n][4] = network(x [n][20]) (host arrays). */
+int ucac_mlp_forward(ucac_mlp* m, const float* x, int64_t n, float* y);
+/* Gradient of the mean squared error over the n samples and 4 outputs
+ * (grad [UCAC_MLP_PARAMS], may be NULL) and the loss; weights unchanged. */
+int ucac_mlp_grad(ucac_mlp* m, const float* x, const float* t, int64_t n, float* grad, double* loss);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) on shuffled mini-batches for `epochs`
+ * passes over the n pairs; *last_loss = mean squared error of the last pass. */
+int ucac_mlp_train(ucac_mlp* m, const float* x, const float* t, int64_t n, int32_t epochs, int32_t batch, double lr,
+                   uint64_t seed, double* last_loss);
+const char* ucac_mlp_last_error(const ucac_mlp* m);
+void ucac_mlp_destroy(ucac_mlp* m);
 
 /* Message of the last error on this handle (or of the last failed create when
  * h is NULL).  Valid until the next call on the handle. */

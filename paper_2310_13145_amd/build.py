@@ -25,6 +25,7 @@ SOURCES = {
     "k_branch.hip": "fast",
     "k_bar.hip": "off",
     "k_ctl.hip": "off",
+    "k_mlp.hip": "off",
 }
 
 COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall",

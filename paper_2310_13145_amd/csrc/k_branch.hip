@@ -17,6 +17,7 @@
 // share the form a v_i^2 + b v_j^2 + v_i v_j (al cos d + be sin d)), so a full
 // evaluation costs about 200 flops.
 #include "ucac_launch.hpp"
+#include "ucac_mlp.hpp"
 
 namespace ucac {
 
@@ -25,7 +26,7 @@ namespace {
 struct Line {
   // flow k = a_k vi^2 + b_k vj^2 + vi vj (al_k cos d + be_k sin d)
   double Gii, Bii, Gij, Bij, Gjj, Bjj, Gji, Bji;
-  double rate2;
+  double rate, rate2;
   double lo0, hi0, lo1, hi1;  // voltage boxes; angles are in [-2pi, 2pi]
   double c[8];
   double rpq, rva, mu, nu0, nu1;
@@ -191,52 +192,19 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
   for (int i = 0; i < 4; ++i) out[i] = z[i];
 }
 
-}  // namespace
-
-__global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p) {
-  if (s.ctl->halt) return;
-  const int TL = n.T * n.L;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  const bool active = idx < TL;
-  int n_eval = 0, n_trial = 0, n_cg = 0, it = 0;
-  if (active) {
-  const int t = idx / n.L, l = idx - t * n.L;
-  const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
-
-  Line L;
-  L.Gii = n.adm[0 * n.L + l]; L.Bii = n.adm[1 * n.L + l]; L.Gij = n.adm[2 * n.L + l]; L.Bij = n.adm[3 * n.L + l];
-  L.Gjj = n.adm[4 * n.L + l]; L.Bjj = n.adm[5 * n.L + l]; L.Gji = n.adm[6 * n.L + l]; L.Bji = n.adm[7 * n.L + l];
-  const double rate = n.rate[l];
-  L.rate2 = rate * rate;
-  L.lo0 = n.vmin[n.from[l]]; L.hi0 = n.vmax[n.from[l]];
-  L.lo1 = n.vmin[n.to[l]]; L.hi1 = n.vmax[n.to[l]];
-  L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu;
-  L.nu0 = s.nuf[idx]; L.nu1 = s.nut[idx];
-  {
-    const double xb[8] = {s.Pbf[idx], s.Qbf[idx], s.Pbt[idx], s.Qbt[idx], s.wb[bi], s.wb[bj], s.thb[bi], s.thb[bj]};
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const double rho = r < 4 ? p.rho_pq : p.rho_va;
-      L.c[r] = xb[r] - s.zB[r * TL + idx] - s.yB[r * TL + idx] / rho;
-    }
-  }
-  const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
-  const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
-
-  double x[4];
-  if (p.warm_start == 1) {
-    x[0] = s.vf[idx]; x[1] = s.vt[idx]; x[2] = s.thf[idx]; x[3] = s.tht[idx];
-  } else {
-    x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-  }
+// Projected trust-region Newton from x (in place).  Returns the iterations taken;
+// conv is set when it stopped at the projected-gradient tolerance.
+__device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
+                             int& n_eval, int& n_trial, int& n_cg, bool& conv) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
-
   double g[4];
   Sym4 H;
   double F = evaluate(L, x, g, H);
-  n_eval = 1;
+  ++n_eval;
   double delta = 1.0;
+  conv = false;
+  int it;
   for (it = 0; it < p.newton_max_iter; ++it) {
     double fr[4];
     int nf = 0;
@@ -248,7 +216,7 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p) {
       nf += out ? 0 : 1;
       pg = out ? pg : fmax(pg, fabs(g[i]));
     }
-    if (pg <= p.gtol) break;
+    if (pg <= p.gtol) { conv = true; break; }
     double d[4];
     steihaug(H, g, fr, nf, delta, d, n_cg);
     double xt[4], sv[4];
@@ -277,35 +245,149 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p) {
       ++n_eval;
     }
   }
+  return it;
+}
 
-  double S, C;
-  sincos(x[2] - x[3], &S, &C);
-  double f0, f1, f2, f3;
-  flows4(L, x[0], x[1], C, S, f0, f1, f2, f3);
-  s.vf[idx] = x[0]; s.vt[idx] = x[1]; s.thf[idx] = x[2]; s.tht[idx] = x[3];
-  s.pf[idx] = f0; s.qf[idx] = f1; s.pt[idx] = f2; s.qt[idx] = f3;
-  s.nuf[idx] = fmax(0.0, L.nu0 + L.mu * (f0 * f0 + f1 * f1 - L.rate2));
-  s.nut[idx] = fmax(0.0, L.nu1 + L.mu * (f2 * f2 + f3 * f3 - L.rate2));
-  s.br_iters[idx] = it;
+// The 20 inputs of the learned start: series conductance and susceptance, line
+// charging, rating, the eight targets (flows, v^2 - 1, angle difference), the
+// line-limit multipliers, voltage bounds, penalties, and the target loading.
+__device__ inline void line_features(const Line& L, float (&f)[MLP_IN]) {
+  f[0] = (float)(0.1 * L.Gii);
+  f[1] = (float)(0.05 * L.Bij);
+  f[2] = (float)(10.0 * (L.Bii + L.Bij));
+  f[3] = (float)(L.rate / 3.0);
+  f[4] = (float)L.c[0];
+  f[5] = (float)L.c[1];
+  f[6] = (float)L.c[2];
+  f[7] = (float)L.c[3];
+  f[8] = (float)(L.c[4] - 1.0);
+  f[9] = (float)(L.c[5] - 1.0);
+  f[10] = (float)(5.0 * (L.c[6] - L.c[7]));
+  f[11] = (float)(L.nu0 / L.mu);
+  f[12] = (float)(L.nu1 / L.mu);
+  f[13] = (float)(L.lo0 - 1.0);
+  f[14] = (float)(L.hi0 - 1.0);
+  f[15] = (float)(L.lo1 - 1.0);
+  f[16] = (float)(L.hi1 - 1.0);
+  f[17] = (float)(log10(L.rpq) - 4.0);
+  f[18] = (float)(log10(L.rva) - 4.0);
+  f[19] = (float)((L.c[0] * L.c[0] + L.c[1] * L.c[1] - L.rate2) / L.rate2);
+}
+
+// The 4 outputs: v_i - 1, v_j - 1, 10 (th_i - c6), 10 (th_j - c7).
+__device__ inline void encode_solution(const Line& L, const double (&x)[4], float (&y)[MLP_OUT]) {
+  y[0] = (float)(x[0] - 1.0);
+  y[1] = (float)(x[1] - 1.0);
+  y[2] = (float)(10.0 * (x[2] - L.c[6]));
+  y[3] = (float)(10.0 * (x[3] - L.c[7]));
+}
+
+}  // namespace
+
+// LEARNED: every wavefront first evaluates the warm-start network for its 64 lines
+// (BF16 MFMA, LDS staging) and starts Newton there; a lane whose Newton does not
+// reach the tolerance restarts from the flat start (the plain method is the fallback).
+template <bool LEARNED>
+__global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) {
+  if (s.ctl->halt) return;
+  const int TL = n.T * n.L;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const bool active = idx < TL;
+  int n_eval = 0, n_trial = 0, n_cg = 0, it = 0, n_fb = 0;
+  Line L = {};
+  L.rate = 1.0; L.rate2 = 1.0; L.mu = 1.0; L.rpq = 1.0; L.rva = 1.0;
+  if (active) {
+    const int t = idx / n.L, l = idx - t * n.L;
+    const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
+    L.Gii = n.adm[0 * n.L + l]; L.Bii = n.adm[1 * n.L + l]; L.Gij = n.adm[2 * n.L + l]; L.Bij = n.adm[3 * n.L + l];
+    L.Gjj = n.adm[4 * n.L + l]; L.Bjj = n.adm[5 * n.L + l]; L.Gji = n.adm[6 * n.L + l]; L.Bji = n.adm[7 * n.L + l];
+    L.rate = n.rate[l];
+    L.rate2 = L.rate * L.rate;
+    L.lo0 = n.vmin[n.from[l]]; L.hi0 = n.vmax[n.from[l]];
+    L.lo1 = n.vmin[n.to[l]]; L.hi1 = n.vmax[n.to[l]];
+    L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu;
+    L.nu0 = s.nuf[idx]; L.nu1 = s.nut[idx];
+    const double xb[8] = {s.Pbf[idx], s.Qbf[idx], s.Pbt[idx], s.Qbt[idx], s.wb[bi], s.wb[bj], s.thb[bi], s.thb[bj]};
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double rho = r < 4 ? p.rho_pq : p.rho_va;
+      L.c[r] = xb[r] - s.zB[r * TL + idx] - s.yB[r * TL + idx] / rho;
+    }
+  }
+  const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
+  const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
+  double x[4];
+  if constexpr (LEARNED) {
+    extern __shared__ __bf16 lds_branch[];
+    float f[MLP_IN], y[MLP_OUT];
+    line_features(L, f);
+    mlp_forward_wave(w, f, lds_branch + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
+    x[0] = 1.0 + (double)y[0];
+    x[1] = 1.0 + (double)y[1];
+    x[2] = L.c[6] + 0.1 * (double)y[2];
+    x[3] = L.c[7] + 0.1 * (double)y[3];
+    if (!(x[0] == x[0] && x[1] == x[1] && x[2] == x[2] && x[3] == x[3])) {
+      x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
+    }
+  } else if (p.warm_start == 1 && active) {
+    x[0] = s.vf[idx]; x[1] = s.vt[idx]; x[2] = s.thf[idx]; x[3] = s.tht[idx];
+  } else {
+    x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
+  }
+  if (active) {
+    bool conv;
+    it = newton(L, lo, hi, x, p, n_eval, n_trial, n_cg, conv);
+    if (LEARNED && !conv) {
+      ++n_fb;
+      x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
+      it += newton(L, lo, hi, x, p, n_eval, n_trial, n_cg, conv);
+    }
+    double S, C;
+    sincos(x[2] - x[3], &S, &C);
+    double f0, f1, f2, f3;
+    flows4(L, x[0], x[1], C, S, f0, f1, f2, f3);
+    s.vf[idx] = x[0]; s.vt[idx] = x[1]; s.thf[idx] = x[2]; s.tht[idx] = x[3];
+    s.pf[idx] = f0; s.qf[idx] = f1; s.pt[idx] = f2; s.qt[idx] = f3;
+    s.nuf[idx] = fmax(0.0, L.nu0 + L.mu * (f0 * f0 + f1 * f1 - L.rate2));
+    s.nut[idx] = fmax(0.0, L.nu1 + L.mu * (f2 * f2 + f3 * f3 - L.rate2));
+    s.br_iters[idx] = it;
+    if (s.log_feat && idx % s.log_stride == s.log_phase) {
+      // (inputs, converged solution) pair for training the learned start
+      const int slot = atomicAdd(s.log_count, 1);
+      if (slot < s.log_cap) {
+        float f[MLP_IN], y[MLP_OUT];
+        line_features(L, f);
+        encode_solution(L, x, y);
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) s.log_feat[(size_t)slot * MLP_IN + k] = f[k];
+#pragma unroll
+        for (int k = 0; k < MLP_OUT; ++k) s.log_targ[(size_t)slot * MLP_OUT + k] = y[k];
+      }
+    }
   }
   // work counters: one wave-level sum and one atomic per wave and counter
-  unsigned long long c[4] = {(unsigned long long)n_eval, (unsigned long long)n_trial, (unsigned long long)n_cg,
-                             (unsigned long long)it};
+  unsigned long long c[5] = {(unsigned long long)n_eval, (unsigned long long)n_trial, (unsigned long long)n_cg,
+                             (unsigned long long)it, (unsigned long long)n_fb};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) atomicAdd(&s.br_count[k], c[k]);
+    for (int k = 0; k < 5; ++k) atomicAdd(&s.br_count[k], c[k]);
   }
 }
 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TL = n.T * n.L;
   if (TL == 0) return;
-  hipLaunchKernelGGL(k_branch, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+  if (p.warm_start == 2) {
+    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
+    hipLaunchKernelGGL(k_branch<true>, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), lds, st, n, s, p, p.mlp);
+  } else {
+    hipLaunchKernelGGL(k_branch<false>, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p, p.mlp);
+  }
 }
 
 }  // namespace ucac

@@ -49,6 +49,8 @@ struct ucac_handle {
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
+  // learned warm start: FP32 parameters and BF16 operand copies
+  void* mlp_mem = nullptr;
   // locality ordering: internal index -> caller's index
   std::vector<int> perm_bus, perm_line, perm_gen;
   std::string err;
@@ -178,7 +180,9 @@ size_t carve(ucac_handle* h, char* base) {
   h->d_state = a.take<double>(h->n_state);
   s.ub_nxt = a.take<double>(3 * T * G);
   s.br_iters = a.take<int>(T * L);
-  s.br_count = a.take<unsigned long long>(4);
+  s.br_count = a.take<unsigned long long>(5);
+  s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
+  s.log_cap = 0; s.log_stride = 1; s.log_phase = 0;
   h->d_ctl = a.take<Ctl>(1);
   s.ctl = h->d_ctl;
   // state views (the state format of ucac_get_state)
@@ -393,7 +397,7 @@ void unpermute_rows(const std::vector<int>& perm, size_t T, const V* src, V* dst
 }
 
 Par kernel_params(const ucac_params& p) {
-  Par k;
+  Par k{};
   k.rho_pq = p.rho_pq; k.rho_va = p.rho_va; k.rho_uc = p.rho_uc; k.rho_cpl = p.rho_cpl; k.mu = p.mu_line;
   k.gtol = p.newton_gtol * std::fmax(1.0, std::fmax(p.rho_pq, p.rho_va));
   k.tau = p.tau; k.theta = p.theta; k.lambda_max = p.lambda_max; k.beta_max = p.beta_max; k.eps_in0 = p.eps_in0;
@@ -426,11 +430,11 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
-hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where) {
+hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
   static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
       launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_gen_dual, launch_finalize, launch_lambda};
-  fns[k](h->net, h->st, h->kp, st);
+  fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
   return e;
@@ -581,7 +585,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   }
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
-      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 4) != hipSuccess)
+      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 5) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
   if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
@@ -792,8 +796,8 @@ int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset) {
   if (!h || !out) return h ? fail(h, UCAC_E_INVAL, "null output") : UCAC_E_INVAL;
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
-  HIP_OR(h, hipMemcpy(out, h->st.br_count, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
-  if (reset) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 4));
+  HIP_OR(h, hipMemcpy(out, h->st.br_count, sizeof(uint64_t) * 5, hipMemcpyDeviceToHost));
+  if (reset) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 5));
   return UCAC_OK;
 }
 
@@ -805,6 +809,295 @@ int ucac_solve_milestones(const ucac_handle* hc, int32_t* first_iter) {
   if (rc) return rc;
   for (int m = 0; m < 3; ++m) first_iter[m] = h->h_ctl->ms_iter[m];
   return UCAC_OK;
+}
+
+// ---- learned warm start ---------------------------------------------------------
+
+namespace {
+struct MlpBufs {
+  float* P;
+  __bf16 *W1b, *W2b, *W3b;
+};
+size_t mlp_bytes() { return sizeof(float) * MLP_PARAMS + sizeof(__bf16) * (64 * 32 + 64 * 64 + 32 * 64) + 1024; }
+MlpBufs mlp_carve(void* base) {
+  char* c = (char*)base;
+  MlpBufs b;
+  b.P = (float*)c; c += ((sizeof(float) * MLP_PARAMS + 255) / 256) * 256;
+  b.W1b = (__bf16*)c; c += sizeof(__bf16) * 64 * 32;
+  b.W2b = (__bf16*)c; c += sizeof(__bf16) * 64 * 64;
+  b.W3b = (__bf16*)c;
+  return b;
+}
+MlpView mlp_view(const MlpBufs& b) {
+  MlpView v;
+  v.W1b = b.W1b; v.W2b = b.W2b; v.W3b = b.W3b;
+  v.b1 = b.P + 64 * 20; v.b2 = b.P + 64 * 20 + 64 + 64 * 64; v.b3 = b.P + 64 * 20 + 64 + 64 * 64 + 64 + 4 * 64;
+  return v;
+}
+}  // namespace
+
+int ucac_set_warmstart(ucac_handle* h, const float* weights, size_t n) {
+  if (!h) return UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  if (!weights) {
+    h->kp.warm_start = h->par.warm_start;
+    return build_graph(h);
+  }
+  if (n != (size_t)MLP_PARAMS) return fail(h, UCAC_E_INVAL, "expected %d weights, got %zu", MLP_PARAMS, n);
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(weights[i])) return fail(h, UCAC_E_INVAL, "weight %zu is not finite", i);
+  if (!h->mlp_mem) {
+    HIP_OR(h, hipMalloc(&h->mlp_mem, mlp_bytes()));
+    HIP_OR(h, hipMemset(h->mlp_mem, 0, mlp_bytes()));
+  }
+  const MlpBufs b = mlp_carve(h->mlp_mem);
+  HIP_OR(h, hipMemcpy(b.P, weights, sizeof(float) * n, hipMemcpyHostToDevice));
+  mlp_launch_pack(b.P, b.W1b, b.W2b, b.W3b, h->stream);
+  HIP_OR(h, hipGetLastError());
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  h->kp.mlp = mlp_view(b);
+  h->kp.warm_start = 2;
+  return build_graph(h);
+}
+
+int ucac_log_pairs(ucac_handle* h, int32_t n_iters, int32_t stride, float* feats, float* targets, int64_t cap,
+                   int64_t* n_logged) {
+  if (!h || !feats || !targets || n_iters < 0 || stride < 1 || cap < 0 || cap > 0x7fffffff)
+    return h ? fail(h, UCAC_E_INVAL, "bad arguments") : UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  int rc = set_ctl(h, 0, h->par.tol);
+  if (rc) return rc;
+  float* d = nullptr;
+  int* cnt = nullptr;
+  const size_t c = (size_t)(cap > 0 ? cap : 1);
+  HIP_OR(h, hipMalloc(&d, sizeof(float) * c * 24));
+  if (hipMalloc(&cnt, sizeof(int)) != hipSuccess) { (void)hipFree(d); return fail(h, UCAC_E_NOMEM, "log counter"); }
+  hipError_t err = hipMemsetAsync(cnt, 0, sizeof(int), h->stream);
+  State sv = h->st;
+  sv.log_feat = d;
+  sv.log_targ = d + c * 20;
+  sv.log_count = cnt;
+  sv.log_cap = (int)cap;
+  sv.log_stride = stride;
+  const char* where = "";
+  for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
+    sv.log_phase = it % stride;
+    for (int k = 0; k < UCAC_N_KERNELS && err == hipSuccess; ++k) err = launch_one(h, k, h->stream, &where, &sv);
+  }
+  int got = 0;
+  if (err == hipSuccess) err = hipMemcpyAsync(&got, cnt, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
+  const int64_t m = got < cap ? got : cap;
+  if (err == hipSuccess && m > 0) err = hipMemcpy(feats, d, sizeof(float) * m * 20, hipMemcpyDeviceToHost);
+  if (err == hipSuccess && m > 0) err = hipMemcpy(targets, d + c * 20, sizeof(float) * m * 4, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  (void)hipFree(cnt);
+  if (err != hipSuccess) return fail(h, UCAC_E_DEVICE, "logging failed at %s: %s", where, hipGetErrorString(err));
+  if (n_logged) *n_logged = m;
+  rc = read_status(h);
+  if (rc) return rc;
+  return check_bad(h);
+}
+
+// ---- the warm-start network on its own (training, inference, gradients) ---------
+
+struct ucac_mlp {
+  int device = 0;
+  hipStream_t st = nullptr;
+  void* mem = nullptr;  // P, BF16 copies
+  float *m1 = nullptr, *m2 = nullptr;
+  int step = 0;
+  std::string err;
+};
+
+namespace {
+int mfail(ucac_mlp* m, int code, const char* what, hipError_t e) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  if (m) m->err = buf; else g_create_error = buf;
+  return code;
+}
+#define MLP_OR(m, call)                                                  \
+  do {                                                                   \
+    hipError_t _e = (call);                                              \
+    if (_e != hipSuccess) return mfail(m, UCAC_E_DEVICE, #call, _e);     \
+  } while (0)
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// device scratch of one call: inputs, targets, indices, gradient slots, gradient, loss
+struct MlpCall {
+  float *X = nullptr, *Y = nullptr, *slots = nullptr, *grad = nullptr;
+  int* idx = nullptr;
+  double* loss = nullptr;
+  ~MlpCall() {
+    for (void* p : {(void*)X, (void*)Y, (void*)slots, (void*)grad, (void*)idx, (void*)loss})
+      if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+int ucac_mlp_create(int32_t device, uint64_t seed, ucac_mlp** out) {
+  if (!out) return UCAC_E_INVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed");
+  ucac_mlp* m = new ucac_mlp();
+  m->device = device;
+  std::vector<float> P(MLP_PARAMS, 0.0f);
+  uint64_t s = seed;
+  auto uni = [&](float bound) { return (float)((double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0) * bound; };
+  for (int i = 0; i < 64 * 20; ++i) P[i] = uni(1.0f / std::sqrt(20.0f));
+  for (int i = 0; i < 64 * 64; ++i) P[64 * 20 + 64 + i] = uni(1.0f / 8.0f);
+  for (int i = 0; i < 4 * 64; ++i) P[64 * 20 + 64 + 64 * 64 + 64 + i] = uni(1.0f / 8.0f);
+  auto bad = [&](hipError_t e, const char* what) { int rc = mfail(m, UCAC_E_DEVICE, what, e); g_create_error = m->err; ucac_mlp_destroy(m); return rc; };
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&m->st, hipStreamNonBlocking)) != hipSuccess) return bad(e, "stream");
+  if ((e = hipMalloc(&m->mem, mlp_bytes())) != hipSuccess) return bad(e, "hipMalloc");
+  if ((e = hipMemset(m->mem, 0, mlp_bytes())) != hipSuccess) return bad(e, "memset");
+  if ((e = hipMalloc(&m->m1, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "hipMalloc");
+  if ((e = hipMalloc(&m->m2, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "hipMalloc");
+  if ((e = hipMemset(m->m1, 0, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "memset");
+  if ((e = hipMemset(m->m2, 0, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "memset");
+  const MlpBufs b = mlp_carve(m->mem);
+  if ((e = hipMemcpy(b.P, P.data(), sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice)) != hipSuccess) return bad(e, "upload");
+  mlp_launch_pack(b.P, b.W1b, b.W2b, b.W3b, m->st);
+  if ((e = hipStreamSynchronize(m->st)) != hipSuccess) return bad(e, "pack");
+  *out = m;
+  return UCAC_OK;
+}
+
+int ucac_mlp_set_weights(ucac_mlp* m, const float* w, size_t n) {
+  if (!m || !w || n != (size_t)MLP_PARAMS) return m ? (m->err = "bad weights", UCAC_E_INVAL) : UCAC_E_INVAL;
+  MLP_OR(m, hipSetDevice(m->device));
+  const MlpBufs b = mlp_carve(m->mem);
+  MLP_OR(m, hipMemcpy(b.P, w, sizeof(float) * n, hipMemcpyHostToDevice));
+  mlp_launch_pack(b.P, b.W1b, b.W2b, b.W3b, m->st);
+  MLP_OR(m, hipStreamSynchronize(m->st));
+  MLP_OR(m, hipMemset(m->m1, 0, sizeof(float) * MLP_PARAMS));
+  MLP_OR(m, hipMemset(m->m2, 0, sizeof(float) * MLP_PARAMS));
+  m->step = 0;
+  return UCAC_OK;
+}
+
+int ucac_mlp_get_weights(const ucac_mlp* mc, float* w, size_t n) {
+  ucac_mlp* m = const_cast<ucac_mlp*>(mc);
+  if (!m || !w || n != (size_t)MLP_PARAMS) return m ? (m->err = "bad buffer", UCAC_E_INVAL) : UCAC_E_INVAL;
+  MLP_OR(m, hipSetDevice(m->device));
+  MLP_OR(m, hipStreamSynchronize(m->st));
+  MLP_OR(m, hipMemcpy(w, mlp_carve(m->mem).P, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return UCAC_OK;
+}
+
+int ucac_mlp_forward(ucac_mlp* m, const float* x, int64_t n, float* y) {
+  if (!m || !x || !y || n < 0 || n > 0x7fffffff) return m ? (m->err = "bad arguments", UCAC_E_INVAL) : UCAC_E_INVAL;
+  if (n == 0) return UCAC_OK;
+  MLP_OR(m, hipSetDevice(m->device));
+  MlpCall c;
+  MLP_OR(m, hipMalloc(&c.X, sizeof(float) * n * 20));
+  MLP_OR(m, hipMalloc(&c.Y, sizeof(float) * n * 4));
+  MLP_OR(m, hipMemcpy(c.X, x, sizeof(float) * n * 20, hipMemcpyHostToDevice));
+  mlp_launch_forward(mlp_view(mlp_carve(m->mem)), c.X, (int)n, c.Y, m->st);
+  MLP_OR(m, hipGetLastError());
+  MLP_OR(m, hipStreamSynchronize(m->st));
+  MLP_OR(m, hipMemcpy(y, c.Y, sizeof(float) * n * 4, hipMemcpyDeviceToHost));
+  return UCAC_OK;
+}
+
+int ucac_mlp_grad(ucac_mlp* m, const float* x, const float* t, int64_t n, float* grad, double* loss) {
+  if (!m || !x || !t || n < 1 || n > (1 << 22)) return m ? (m->err = "bad arguments", UCAC_E_INVAL) : UCAC_E_INVAL;
+  MLP_OR(m, hipSetDevice(m->device));
+  MlpCall c;
+  const int waves = (int)((n + 63) / 64);
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  MLP_OR(m, hipMalloc(&c.X, sizeof(float) * n * 20));
+  MLP_OR(m, hipMalloc(&c.Y, sizeof(float) * n * 4));
+  MLP_OR(m, hipMalloc(&c.idx, sizeof(int) * n));
+  MLP_OR(m, hipMalloc(&c.slots, sizeof(float) * waves * MLP_SLOT));
+  MLP_OR(m, hipMalloc(&c.grad, sizeof(float) * MLP_PARAMS));
+  MLP_OR(m, hipMalloc(&c.loss, sizeof(double)));
+  MLP_OR(m, hipMemcpy(c.X, x, sizeof(float) * n * 20, hipMemcpyHostToDevice));
+  MLP_OR(m, hipMemcpy(c.Y, t, sizeof(float) * n * 4, hipMemcpyHostToDevice));
+  MLP_OR(m, hipMemcpy(c.idx, idx.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  const MlpBufs b = mlp_carve(m->mem);
+  mlp_launch_train(mlp_view(b), c.X, c.Y, c.idx, (int)n, (float)(2.0 / (4.0 * (double)n)), c.slots, m->st);
+  mlp_launch_reduce(c.slots, waves, c.grad, c.loss, b.P, m->m1, m->m2, 0, 0.0f, b.W1b, b.W2b, b.W3b, m->st);
+  MLP_OR(m, hipGetLastError());
+  MLP_OR(m, hipStreamSynchronize(m->st));
+  double ls = 0.0;
+  MLP_OR(m, hipMemcpy(&ls, c.loss, sizeof(double), hipMemcpyDeviceToHost));
+  if (grad) MLP_OR(m, hipMemcpy(grad, c.grad, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
+  if (loss) *loss = ls / (4.0 * (double)n);
+  return UCAC_OK;
+}
+
+int ucac_mlp_train(ucac_mlp* m, const float* x, const float* t, int64_t n, int32_t epochs, int32_t batch, double lr,
+                   uint64_t seed, double* last_loss) {
+  if (!m || !x || !t || n < 1 || n > 0x7fffffff || epochs < 0 || batch < 1 || !(lr > 0.0))
+    return m ? (m->err = "bad arguments", UCAC_E_INVAL) : UCAC_E_INVAL;
+  MLP_OR(m, hipSetDevice(m->device));
+  MlpCall c;
+  const int waves = (batch + 63) / 64;
+  MLP_OR(m, hipMalloc(&c.X, sizeof(float) * n * 20));
+  MLP_OR(m, hipMalloc(&c.Y, sizeof(float) * n * 4));
+  MLP_OR(m, hipMalloc(&c.idx, sizeof(int) * n));
+  MLP_OR(m, hipMalloc(&c.slots, sizeof(float) * waves * MLP_SLOT));
+  MLP_OR(m, hipMalloc(&c.loss, sizeof(double) * 2));
+  MLP_OR(m, hipMemcpy(c.X, x, sizeof(float) * n * 20, hipMemcpyHostToDevice));
+  MLP_OR(m, hipMemcpy(c.Y, t, sizeof(float) * n * 4, hipMemcpyHostToDevice));
+  const MlpBufs b = mlp_carve(m->mem);
+  const MlpView v = mlp_view(b);
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  uint64_t rs = seed;
+  double epoch_loss = 0.0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[splitmix(rs) % (uint64_t)(i + 1)]);  // Fisher-Yates
+    MLP_OR(m, hipMemcpyAsync(c.idx, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, m->st));
+    std::vector<double> bl;
+    for (int64_t s0 = 0; s0 < n; s0 += batch) {
+      const int nb = (int)std::min<int64_t>(batch, n - s0);
+      mlp_launch_train(v, c.X, c.Y, c.idx + s0, nb, (float)(2.0 / (4.0 * nb)), c.slots, m->st);
+      ++m->step;
+      mlp_launch_reduce(c.slots, (nb + 63) / 64, nullptr, c.loss, b.P, m->m1, m->m2, m->step, (float)lr, b.W1b, b.W2b,
+                        b.W3b, m->st);
+      MLP_OR(m, hipGetLastError());
+      if (e == epochs - 1) {
+        double ls = 0.0;
+        MLP_OR(m, hipMemcpyAsync(&ls, c.loss, sizeof(double), hipMemcpyDeviceToHost, m->st));
+        MLP_OR(m, hipStreamSynchronize(m->st));
+        bl.push_back(ls);
+      }
+    }
+    if (e == epochs - 1) {
+      epoch_loss = 0.0;
+      for (double v2 : bl) epoch_loss += v2;
+      epoch_loss /= 4.0 * (double)n;
+    }
+    MLP_OR(m, hipStreamSynchronize(m->st));  // the next permutation reuses the index buffer
+  }
+  MLP_OR(m, hipStreamSynchronize(m->st));
+  if (last_loss) *last_loss = epoch_loss;
+  return UCAC_OK;
+}
+
+const char* ucac_mlp_last_error(const ucac_mlp* m) { return m ? m->err.c_str() : g_create_error.c_str(); }
+
+void ucac_mlp_destroy(ucac_mlp* m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  if (m->st) (void)hipStreamSynchronize(m->st);
+  if (m->mem) (void)hipFree(m->mem);
+  if (m->m1) (void)hipFree(m->m1);
+  if (m->m2) (void)hipFree(m->m2);
+  if (m->st) (void)hipStreamDestroy(m->st);
+  delete m;
 }
 
 const char* ucac_last_error(const ucac_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
@@ -820,6 +1113,7 @@ void ucac_destroy(ucac_handle* h) {
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_sc) (void)hipHostFree(h->h_sc);
   if (h->arena) (void)hipFree(h->arena);
+  if (h->mlp_mem) (void)hipFree(h->mlp_mem);
   delete h;
 }
 

@@ -67,15 +67,32 @@ struct State {
   double* sc;                                                  // [NSC]
   double* ub_nxt;                                              // [3][T][G] new relaxed commitments
   int* br_iters;                                               // [T][L]
-  unsigned long long* br_count;                                // [4] running totals: evaluations, trial evaluations, CG its, Newton its
+  unsigned long long* br_count;  // [5] running totals: evaluations, trial evaluations, CG its, Newton its, learned-start fallbacks
+  float* log_feat;               // null, or [log_cap][20] logged inputs of the learned start
+  float* log_targ;               // [log_cap][4] logged solutions
+  int* log_count;
+  int log_cap, log_stride, log_phase;
   Ctl* ctl;
+};
+
+// Device view of the learned warm-start network: BF16 weights packed for the
+// MFMA B operand (W1 [64][32] with zero columns >= 20, W2 [64][64], W3 [32][64]
+// with zero rows >= 4) and FP32 biases.
+struct MlpView {
+  const __bf16* W1b;
+  const __bf16* W2b;
+  const __bf16* W3b;
+  const float* b1;
+  const float* b2;
+  const float* b3;
 };
 
 struct Par {
   double rho_pq, rho_va, rho_uc, rho_cpl, mu;
   double gtol;  // absolute projected-gradient tolerance
   double tau, theta, lambda_max, beta_max, eps_in0;
-  int newton_max_iter, max_inner, warm_start;
+  int newton_max_iter, max_inner, warm_start;  // warm_start 2: learned start from mlp
+  MlpView mlp;
 };
 
 // ---- reductions -------------------------------------------------------------

@@ -90,9 +90,24 @@ def lib():
         L.ucac_kernel_times.argtypes = [vp, C.c_int32, vp, C.c_int32]
         L.ucac_branch_counters.argtypes = [vp, vp, C.c_int32]
         L.ucac_solve_milestones.argtypes = [vp, vp]
+        fp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_int64)
+        L.ucac_set_warmstart.argtypes = [vp, vp, C.c_size_t]
+        L.ucac_log_pairs.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, i64p]
+        L.ucac_mlp_create.argtypes = [C.c_int32, C.c_uint64, C.POINTER(vp)]
+        L.ucac_mlp_set_weights.argtypes = [vp, vp, C.c_size_t]
+        L.ucac_mlp_get_weights.argtypes = [vp, vp, C.c_size_t]
+        L.ucac_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+        L.ucac_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, dp]
+        L.ucac_mlp_train.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, dp]
+        L.ucac_mlp_last_error.argtypes = [vp]
+        L.ucac_mlp_last_error.restype = C.c_char_p
+        L.ucac_mlp_destroy.argtypes = [vp]
+        L.ucac_mlp_destroy.restype = None
         for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
                      "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
-                     "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones"):
+                     "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones",
+                     "ucac_set_warmstart", "ucac_log_pairs", "ucac_mlp_create", "ucac_mlp_set_weights",
+                     "ucac_mlp_get_weights", "ucac_mlp_forward", "ucac_mlp_grad", "ucac_mlp_train"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -238,9 +253,89 @@ def ucac_kernel_times(h, n_iters):
 
 
 def ucac_branch_counters(h, reset=False):
-    out = np.zeros(4, dtype=np.uint64)
+    out = np.zeros(5, dtype=np.uint64)
     _check(lib().ucac_branch_counters(h, _ptr(out), int(bool(reset))), h)
-    return dict(evals=int(out[0]), trials=int(out[1]), cg=int(out[2]), newton=int(out[3]))
+    return dict(evals=int(out[0]), trials=int(out[1]), cg=int(out[2]), newton=int(out[3]), fallbacks=int(out[4]))
+
+
+MLP_PARAMS = 5764
+MLP_IN, MLP_OUT = 20, 4
+
+
+def ucac_set_warmstart(h, weights):
+    """Use the learned Newton start with these FP32 weights (None: back to the configured start)."""
+    if weights is None:
+        _check(lib().ucac_set_warmstart(h, None, 0), h)
+        return
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(lib().ucac_set_warmstart(h, _ptr(w), w.size), h)
+
+
+def ucac_log_pairs(h, n_iters, stride, cap):
+    """Run n_iters inner iterations and return the logged (features [m, 20], targets [m, 4])."""
+    f = np.zeros((max(cap, 0), MLP_IN), dtype=np.float32)
+    t = np.zeros((max(cap, 0), MLP_OUT), dtype=np.float32)
+    n = C.c_int64(0)
+    _check(lib().ucac_log_pairs(h, int(n_iters), int(stride), _ptr(f), _ptr(t), int(cap), C.byref(n)), h)
+    return f[:n.value], t[:n.value]
+
+
+def _mcheck(rc, m):
+    if rc != UCAC_OK:
+        s = lib().ucac_mlp_last_error(m)
+        raise UcacError(rc, s.decode() if s else "")
+    return rc
+
+
+class WarmStartNet:
+    """The learned line warm-start network on one GPU (FP32 master weights, BF16 copies)."""
+
+    def __init__(self, seed=0, device=0):
+        m = C.c_void_p()
+        _mcheck(lib().ucac_mlp_create(int(device), int(seed) & (2**64 - 1), C.byref(m)), None)
+        self.m = m
+
+    def close(self):
+        if getattr(self, "m", None):
+            lib().ucac_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        w = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _mcheck(lib().ucac_mlp_get_weights(self.m, _ptr(w), w.size), self.m)
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _mcheck(lib().ucac_mlp_set_weights(self.m, _ptr(w), w.size), self.m)
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, MLP_IN)
+        y = np.zeros((x.shape[0], MLP_OUT), dtype=np.float32)
+        _mcheck(lib().ucac_mlp_forward(self.m, _ptr(x), x.shape[0], _ptr(y)), self.m)
+        return y
+
+    def grad(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, MLP_IN)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, MLP_OUT)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        ls = C.c_double(0.0)
+        _mcheck(lib().ucac_mlp_grad(self.m, _ptr(x), _ptr(t), x.shape[0], _ptr(g), C.byref(ls)), self.m)
+        return g, ls.value
+
+    def train(self, x, t, epochs=10, batch=256, lr=1e-3, seed=0):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, MLP_IN)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, MLP_OUT)
+        ls = C.c_double(0.0)
+        _mcheck(lib().ucac_mlp_train(self.m, _ptr(x), _ptr(t), x.shape[0], int(epochs), int(batch), float(lr),
+                                     int(seed) & (2**64 - 1), C.byref(ls)), self.m)
+        return ls.value
 
 
 def ucac_solve_milestones(h):
@@ -310,3 +405,12 @@ class Solver:
     def branch_iters(self):
         N, L, G, T = self.dims
         return ucac_get_branch_iters(self.h, L, T)
+
+    def set_warmstart(self, weights):
+        ucac_set_warmstart(self.h, weights)
+
+    def log_pairs(self, n_iters, stride=1, cap=None):
+        N, L, G, T = self.dims
+        if cap is None:
+            cap = n_iters * ((L * T + stride - 1) // stride)
+        return ucac_log_pairs(self.h, n_iters, stride, cap)
