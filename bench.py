@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -30,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic flops of the line kernel, counted from its source (one flop per
 # +, -, *, /, sqrt, sin, cos; an FMA counts two; compile-time zero terms dropped):
 FLOP_EVAL = 349      # value + gradient + 10-entry Hessian at one point (inactive line limits)
-FLOP_TRIAL = 75      # value only at a trial point
+FLOP_TRIAL = 75      # value only at a trial point (what a rejected trial needs)
 FLOP_CG = 80         # one Steihaug-Toint CG iteration on the 4x4 system
 FLOP_NEWTON = 80     # per trust-region iteration: projection, predicted reduction, ratio, radius
 FLOP_LANE = 70       # per solve: targets from duplicates/multipliers, start, final flows, nu update
@@ -44,6 +46,32 @@ BYTES_GEN_DUAL = 8 * 66
 BYTES_BUS_PER_END = 8 * 28  # per incident line end; plus per unit 24 and per bus 6 doubles
 
 
+# HBM bytes per dispatch of the plain-start line kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged over the dispatches of the
+# mesh2000_T24 bench command), each scaled by the ratio of true to counted bytes of a
+# plain copy kernel of known size.  They describe the kernel source they were taken
+# on (hash below) and are reported as null once that source has changed.
+BRANCH_COUNTERS = {"source_sha256": "bc3a6d8222698e5d9c67525fe5bef3fa9ab77a98688bb7f84a96fa8e645ef9ca",
+                   "fetch_kib": 7879.05, "write_kib": 6450.0, "fetch_scale": 2.0, "write_scale": 1.0}
+BRANCH_SOURCES = ("k_branch.hip", "ucac_dev.hpp", "ucac_mlp.hpp", "ucac_launch.hpp")
+
+
+def branch_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in BRANCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_13145_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def branch_traffic():
+    c = BRANCH_COUNTERS
+    if not c or c["source_sha256"] != branch_source_hash():
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +83,13 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iters", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start evaluation")
+    ap.add_argument("--train-instances", type=int, default=2)
+    ap.add_argument("--log-iters", type=int, default=300)
+    ap.add_argument("--log-stride", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--learned-steps", type=int, default=200)
+    ap.add_argument("--learned-max-iters", type=int, default=4000)
     return ap.parse_args()
 
 
@@ -97,13 +132,95 @@ def time_to_tol(ucac, torch, inst, args):
     return res
 
 
+def _timed_steps(solver, torch, warmup, steps):
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def learned_start(ucac, synth, torch, args):
+    """Learned Newton start: pairs logged by the method on 2000-bus T=24 instances of
+    other seeds, the network trained on the GPU, then plain (flat start) against
+    learned start on the 2000-bus and the 10000-bus T=48 workloads: iteration rate,
+    Newton work per solve, and time to the residual milestones from the cold start."""
+    out = {}
+    t0 = time.perf_counter()
+    X, Y = [], []
+    for k in range(args.train_instances):
+        s = ucac.Solver(synth.training_instance(2, k))
+        f, t = s.log_pairs(args.log_iters, stride=args.log_stride)
+        X.append(f), Y.append(t)
+        s.close()
+    X, Y = np.vstack(X), np.vstack(Y)
+    t_log = time.perf_counter() - t0
+    net = ucac.WarmStartNet(seed=0)
+    _, loss0 = net.grad(X[:65536], Y[:65536])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = net.train(X, Y, epochs=args.epochs, batch=4096, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w = net.get_weights()
+    net.close()
+    out["training"] = {"pairs": int(X.shape[0]), "instances": args.train_instances,
+                       "source": f"2000-bus T=24 instances of other seeds, {args.log_iters} iterations, every "
+                                 f"{args.log_stride}th solve", "log_seconds": t_log, "train_seconds": t_train,
+                       "epochs": args.epochs, "batch": 4096, "mse_before": loss0, "mse_last_epoch": loss}
+    del X, Y
+    for cfg in (2, 4):
+        inst = synth.config_instance(cfg)
+        name = synth.CONFIGS[cfg]["name"]
+        lanes = inst["n_line"] * inst["T"]
+        res = {}
+        for label in ("plain", "learned"):
+            s = ucac.Solver(inst)
+            if label == "learned":
+                s.set_warmstart(w)
+            s.branch_counters(reset=True)
+            sec = _timed_steps(s, torch, 20, args.learned_steps)
+            cnt = s.branch_counters(reset=True)
+            kt = s.kernel_times(20)
+            n_it = 20 + 20 + args.learned_steps
+            res[label] = {"iters_per_s": 1.0 / sec, "ms_per_iter": 1e3 * sec, "branch_ms": kt["branch"],
+                          "newton_per_solve": cnt["newton"] / (n_it - 20) / lanes,
+                          "fallbacks_per_iter": cnt["fallbacks"] / (n_it - 20)}
+            s.close()
+            # time to the milestones from the cold start, same stopping rule
+            s = ucac.Solver(inst)
+            if label == "learned":
+                s.set_warmstart(w)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, iters = s.solve(args.tol, args.learned_max_iters)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ms = s.milestones()
+            rp, rd, zinf, obj = s.residuals()
+            res[label].update({"solve_iters": iters, "solve_seconds": el, "converged": rc == 0, "r_p": rp, "r_d": rd,
+                               "objective": obj, "first_iter_below": ms,
+                               "seconds_to": {k: (v * el / max(iters, 1) if v > 0 else None) for k, v in ms.items()}})
+            s.close()
+        p, l = res["plain"], res["learned"]
+        res["speedup_per_iter"] = p["ms_per_iter"] / l["ms_per_iter"]
+        res["speedup_branch_kernel"] = p["branch_ms"] / l["branch_ms"]
+        res["speedup_time_to"] = {k: (p["seconds_to"][k] / l["seconds_to"][k]
+                                      if p["seconds_to"][k] and l["seconds_to"][k] else None)
+                                  for k in p["seconds_to"]}
+        res["same_trajectory"] = p["first_iter_below"] == l["first_iter_below"]
+        out[name] = res
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the workload is one "
               "instance on one MI355X; see DESIGN.md for how it would shard", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+
     import torch
     from paper_2310_13145_amd import synth, ucac
 
@@ -113,6 +230,7 @@ def main():
 
     solver = ucac.Solver(inst)
     solver.step(args.warmup)
+    state0 = solver.get_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.step(args.steps)
@@ -130,13 +248,19 @@ def main():
     dt_warm = time.perf_counter() - t0
     warm.close()
 
-    # profiled pass: the same iterations kernel by kernel, HIP events on the library stream
+    # profiled pass: the iterations of the timed region again (same starting state, so the
+    # same Newton work), kernel by kernel with HIP events on the library's stream
+    solver.set_state(state0)
     solver.branch_counters(reset=True)
     ktimes = solver.kernel_times(args.steps)
     cnt = solver.branch_counters(reset=True)
     prof_ms_per_step = sum(ktimes.values())
     lanes = T * L
-    flops_per_launch = (cnt["evals"] * FLOP_EVAL + cnt["trials"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
+    # the kernel evaluates value, gradient and Hessian at every trial point and once more
+    # after a rejection; the method needs the full evaluation at the start and at accepted
+    # points and only the value at rejected ones, which is what is counted
+    full = cnt["evals"] - 2 * cnt["rejected"]
+    flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
                         cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
     br_s = ktimes["branch"] * 1e-3
     achieved = flops_per_launch / br_s / 1e12
@@ -170,7 +294,7 @@ def main():
                    "branch_solves_per_step": lanes, "newton_start": "flat (plain method)"},
         "roofline": {"bound": "alu", "kernel": "branch (trust-region Newton, one lane per line-period)",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": branch_traffic(),
                      "flops_per_launch": flops_per_launch, "launch_ms": ktimes["branch"],
                      "newton_iters_per_solve": cnt["newton"] / args.steps / lanes},
         "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps},
@@ -182,6 +306,9 @@ def main():
     if not args.no_solve:
         out["time_to_tol"] = time_to_tol(ucac, torch, inst, args)
         out["time_to_tol_mesh118_T24"] = time_to_tol(ucac, torch, synth.config_instance(1), args)
+
+    if not args.no_learned:
+        out["learned_start"] = learned_start(ucac, synth, torch, args)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)

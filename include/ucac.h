@@ -155,10 +155,11 @@ int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
 int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots);
 
 /* Running totals of the line kernel's work since create or the last reset:
- * out[0] full evaluations (value, gradient, Hessian), out[1] trial evaluations
- * (value only), out[2] CG iterations, out[3] Newton iterations, out[4] learned
- * starts that fell back to the flat start (out has 5 slots).  reset != 0 zeroes
- * them after reading. */
+ * out[0] evaluations of value, gradient and Hessian (one at the start of each
+ * solve, one at every trial point, one more after each rejected trial), out[1]
+ * rejected trial steps, out[2] CG iterations, out[3] Newton iterations, out[4]
+ * learned starts that fell back to the flat start (out has 5 slots).  reset != 0
+ * zeroes them after reading. */
 int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
 
 /* After ucac_solve (or ucac_step): first_iter[m] (m = 0, 1, 2) receives the first

@@ -24,12 +24,14 @@ namespace ucac {
 namespace {
 
 struct Line {
-  // flow k = a_k vi^2 + b_k vj^2 + vi vj (al_k cos d + be_k sin d)
-  double Gii, Bii, Gij, Bij, Gjj, Bjj, Gji, Bji;
+  // flow k = a_k vi^2 + b_k vj^2 + vi vj (al_k cos d + be_k sin d).  Lines are pi-models
+  // without taps or phase shifts, so the admittance blocks are symmetric:
+  // G_ii = G_jj = G, G_ij = G_ji = -G, B_ii = B_jj = Bs, B_ij = B_ji = Bm.
+  double G, Bs, Bm;
   double rate, rate2;
   double lo0, hi0, lo1, hi1;  // voltage boxes; angles are in [-2pi, 2pi]
   double c[8];
-  double rpq, rva, mu, nu0, nu1;
+  double rpq, rva, mu, inv2mu, nu0, nu1;
 };
 
 struct Sym4 {
@@ -39,26 +41,10 @@ struct Sym4 {
 __device__ inline void flows4(const Line& L, double vi, double vj, double C, double S, double& f0, double& f1,
                               double& f2, double& f3) {
   const double vv = vi * vj, vi2 = vi * vi, vj2 = vj * vj;
-  f0 = L.Gii * vi2 + vv * (L.Gij * C + L.Bij * S);
-  f1 = -L.Bii * vi2 + vv * (-L.Bij * C + L.Gij * S);
-  f2 = L.Gjj * vj2 + vv * (L.Gji * C - L.Bji * S);
-  f3 = -L.Bjj * vj2 + vv * (-L.Bji * C - L.Gji * S);
-}
-
-__device__ inline double objective(const Line& L, const double (&x)[4]) {
-  double S, C;
-  sincos(x[2] - x[3], &S, &C);
-  double f0, f1, f2, f3;
-  flows4(L, x[0], x[1], C, S, f0, f1, f2, f3);
-  const double r0 = f0 - L.c[0], r1 = f1 - L.c[1], r2 = f2 - L.c[2], r3 = f3 - L.c[3];
-  double F = 0.5 * L.rpq * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
-  const double r4 = x[0] * x[0] - L.c[4], r5 = x[1] * x[1] - L.c[5];
-  const double r6 = x[2] - L.c[6], r7 = x[3] - L.c[7];
-  F += 0.5 * L.rva * (r4 * r4 + r5 * r5 + r6 * r6 + r7 * r7);
-  const double hf = f0 * f0 + f1 * f1 - L.rate2, ht = f2 * f2 + f3 * f3 - L.rate2;
-  const double tf = fmax(L.nu0 + L.mu * hf, 0.0), tt = fmax(L.nu1 + L.mu * ht, 0.0);
-  F += (tf * tf - L.nu0 * L.nu0) / (2.0 * L.mu) + (tt * tt - L.nu1 * L.nu1) / (2.0 * L.mu);
-  return F;
+  f0 = L.G * vi2 + vv * (-L.G * C + L.Bm * S);
+  f1 = -L.Bs * vi2 + vv * (-L.Bm * C - L.G * S);
+  f2 = L.G * vj2 + vv * (-L.G * C - L.Bm * S);
+  f3 = -L.Bs * vj2 + vv * (-L.Bm * C + L.G * S);
 }
 
 __device__ inline void rank1(Sym4& H, double w, const double (&v)[4]) {
@@ -74,10 +60,10 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
   sincos(x[2] - x[3], &S, &C);
   const double vv = vi * vj;
   // per-flow (a, b, al, be)
-  const double a[4] = {L.Gii, -L.Bii, 0.0, 0.0};
-  const double b[4] = {0.0, 0.0, L.Gjj, -L.Bjj};
-  const double al[4] = {L.Gij, -L.Bij, L.Gji, -L.Bji};
-  const double be[4] = {L.Bij, L.Gij, -L.Bji, -L.Gji};
+  const double a[4] = {L.G, -L.Bs, 0.0, 0.0};
+  const double b[4] = {0.0, 0.0, L.G, -L.Bs};
+  const double al[4] = {-L.G, -L.Bm, -L.G, -L.Bm};
+  const double be[4] = {L.Bm, -L.G, -L.Bm, L.G};
   double f[4], gf[4][4], T[4], Td[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -100,7 +86,7 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
     const double h = f[kp] * f[kp] + f[kq] * f[kq] - L.rate2;
     const double tm = nu + L.mu * h;
     const double tp = tm > 0.0 ? tm : 0.0;
-    F += 0.5 * L.rpq * (rP * rP + rQ * rQ) + (tp * tp - nu * nu) / (2.0 * L.mu);
+    F += 0.5 * L.rpq * (rP * rP + rQ * rQ) + (tp * tp - nu * nu) * L.inv2mu;
     w[kp] = L.rpq * rP + 2.0 * tp * f[kp];
     w[kq] = L.rpq * rQ + 2.0 * tp * f[kq];
     const double gn = L.rpq + 2.0 * tp;
@@ -160,7 +146,7 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 #pragma unroll
   for (int i = 0; i < 4; ++i) { r[i] = fr[i] * g[i]; d[i] = -r[i]; }
   double rr = dot(r, r);
-  const double tol = 1e-12 * sqrt(rr);
+  const double tol2 = 1e-24 * rr, delta2 = delta * delta;  // ||r|| <= 1e-12 ||r0||, ||z|| >= delta
   for (int j = 0; j < nf; ++j) {
     ++cg_its;
     symv(H, d, Hd);
@@ -171,10 +157,10 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
     const double alpha = rr / dHd;
 #pragma unroll
     for (int i = 0; i < 4; ++i) zn[i] = z[i] + alpha * d[i];
-    if (dHd <= 0.0 || sqrt(dot(zn, zn)) >= delta) {
+    if (dHd <= 0.0 || dot(zn, zn) >= delta2) {
       // to the boundary along d: ||z + tau d|| = delta
       const double zd = dot(z, d), dd = dot(d, d), zz = dot(z, z);
-      const double tau = (-zd + sqrt(zd * zd + dd * (delta * delta - zz))) / dd;
+      const double tau = (-zd + sqrt(zd * zd + dd * (delta2 - zz))) / dd;
 #pragma unroll
       for (int i = 0; i < 4; ++i) out[i] = z[i] + tau * d[i];
       return;
@@ -182,7 +168,7 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 #pragma unroll
     for (int i = 0; i < 4; ++i) { r[i] += alpha * Hd[i]; z[i] = zn[i]; }
     const double rr_new = dot(r, r);
-    if (sqrt(rr_new) <= tol) break;
+    if (rr_new <= tol2) break;
     const double beta = rr_new / rr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = -r[i] + beta * d[i];
@@ -193,19 +179,44 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 }
 
 // Projected trust-region Newton from x (in place).  Returns the iterations taken;
-// conv is set when it stopped at the projected-gradient tolerance.
+// conv is set when it stopped at the projected-gradient tolerance.  There is one
+// evaluation site: value, gradient and Hessian are formed at every trial point in
+// one pass (nearly every trial is accepted), and after a rejected trial at x again.
 __device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
-                             int& n_eval, int& n_trial, int& n_cg, bool& conv) {
+                             int& n_eval, int& n_rej, int& n_cg, bool& conv) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
-  double g[4];
+  double g[4], xe[4];
   Sym4 H;
-  double F = evaluate(L, x, g, H);
-  ++n_eval;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xe[i] = x[i];
+  double F = 0.0, pred = 0.0, snorm = 0.0;
   double delta = 1.0;
+  bool trial = false;
   conv = false;
-  int it;
-  for (it = 0; it < p.newton_max_iter; ++it) {
+  int it = 0;
+  for (;;) {
+    const double Fe = evaluate(L, xe, g, H);
+    ++n_eval;
+    if (trial) {
+      const double ratio = pred > 0.0 ? (pred <= 1e-12 * fabs(F) ? 1.0 : (F - Fe) / pred) : -1.0;
+      if (ratio < 0.25) delta = 0.25 * snorm;
+      else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
+      trial = false;
+      if (ratio >= 1e-4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = xe[i];
+        F = Fe;
+      } else {
+        ++n_rej;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xe[i] = x[i];
+        continue;  // gradient and Hessian at x again
+      }
+    } else {
+      F = Fe;
+    }
+    if (it >= p.newton_max_iter) break;
     double fr[4];
     int nf = 0;
     double pg = 0.0;
@@ -219,31 +230,22 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
     if (pg <= p.gtol) { conv = true; break; }
     double d[4];
     steihaug(H, g, fr, nf, delta, d, n_cg);
-    double xt[4], sv[4];
+    double sv[4];
     double sinf = 0.0, xinf = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      xt[i] = clampd(x[i] + d[i], lo[i], hi[i]);
-      sv[i] = xt[i] - x[i];
+      xe[i] = clampd(x[i] + d[i], lo[i], hi[i]);
+      sv[i] = xe[i] - x[i];
       sinf = fmax(sinf, fabs(sv[i]));
       xinf = fmax(xinf, fabs(x[i]));
     }
     if (sinf <= 1e-15 * (1.0 + xinf)) break;
     double Hs[4];
     symv(H, sv, Hs);
-    const double pred = -(dot(g, sv) + 0.5 * dot(sv, Hs));
-    const double Ft = objective(L, xt);
-    ++n_trial;
-    const double ratio = pred > 0.0 ? (pred <= 1e-12 * fabs(F) ? 1.0 : (F - Ft) / pred) : -1.0;
-    const double snorm = sqrt(dot(sv, sv));
-    if (ratio < 0.25) delta = 0.25 * snorm;
-    else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
-    if (ratio >= 1e-4) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = xt[i];
-      F = evaluate(L, x, g, H);
-      ++n_eval;
-    }
+    pred = -(dot(g, sv) + 0.5 * dot(sv, Hs));
+    snorm = sqrt(dot(sv, sv));
+    trial = true;
+    ++it;
   }
   return it;
 }
@@ -252,9 +254,9 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
 // charging, rating, the eight targets (flows, v^2 - 1, angle difference), the
 // line-limit multipliers, voltage bounds, penalties, and the target loading.
 __device__ inline void line_features(const Line& L, float (&f)[MLP_IN]) {
-  f[0] = (float)(0.1 * L.Gii);
-  f[1] = (float)(0.05 * L.Bij);
-  f[2] = (float)(10.0 * (L.Bii + L.Bij));
+  f[0] = (float)(0.1 * L.G);
+  f[1] = (float)(0.05 * L.Bm);
+  f[2] = (float)(10.0 * (L.Bs + L.Bm));
   f[3] = (float)(L.rate / 3.0);
   f[4] = (float)L.c[0];
   f[5] = (float)L.c[1];
@@ -284,28 +286,32 @@ __device__ inline void encode_solution(const Line& L, const double (&x)[4], floa
 
 }  // namespace
 
-// LEARNED: every wavefront first evaluates the warm-start network for its 64 lines
-// (BF16 MFMA, LDS staging) and starts Newton there; a lane whose Newton does not
-// reach the tolerance restarts from the flat start (the plain method is the fallback).
-template <bool LEARNED>
-__global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) {
+// Newton start: START_FLAT (mid-box voltages, zero angles), START_PREV (the line's
+// previous solution) or START_LEARNED: every wavefront first evaluates the warm-start
+// network for its 64 lines (BF16 MFMA, LDS staging) and starts Newton there; a lane
+// whose Newton does not reach the tolerance restarts from the flat start (the plain
+// method is the fallback).  One instantiation per start keeps the plain kernel free
+// of the others' code and registers.
+enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
+
+template <int START>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_branch(Net n, State s, Par p, Mlp w) {
   if (s.ctl->halt) return;
   const int TL = n.T * n.L;
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   const bool active = idx < TL;
-  int n_eval = 0, n_trial = 0, n_cg = 0, it = 0, n_fb = 0;
+  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0;
   Line L = {};
-  L.rate = 1.0; L.rate2 = 1.0; L.mu = 1.0; L.rpq = 1.0; L.rva = 1.0;
+  L.rate = 1.0; L.rate2 = 1.0;
+  L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu; L.inv2mu = 0.5 / p.mu;  // uniform: scalar registers
   if (active) {
     const int t = idx / n.L, l = idx - t * n.L;
     const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
-    L.Gii = n.adm[0 * n.L + l]; L.Bii = n.adm[1 * n.L + l]; L.Gij = n.adm[2 * n.L + l]; L.Bij = n.adm[3 * n.L + l];
-    L.Gjj = n.adm[4 * n.L + l]; L.Bjj = n.adm[5 * n.L + l]; L.Gji = n.adm[6 * n.L + l]; L.Bji = n.adm[7 * n.L + l];
+    L.G = n.adm[0 * n.L + l]; L.Bs = n.adm[1 * n.L + l]; L.Bm = n.adm[3 * n.L + l];
     L.rate = n.rate[l];
     L.rate2 = L.rate * L.rate;
     L.lo0 = n.vmin[n.from[l]]; L.hi0 = n.vmax[n.from[l]];
     L.lo1 = n.vmin[n.to[l]]; L.hi1 = n.vmax[n.to[l]];
-    L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu;
     L.nu0 = s.nuf[idx]; L.nu1 = s.nut[idx];
     const double xb[8] = {s.Pbf[idx], s.Qbf[idx], s.Pbt[idx], s.Qbt[idx], s.wb[bi], s.wb[bj], s.thb[bi], s.thb[bj]};
 #pragma unroll
@@ -317,7 +323,7 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) 
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
   double x[4];
-  if constexpr (LEARNED) {
+  if constexpr (START == START_LEARNED) {
     extern __shared__ __bf16 lds_branch[];
     float f[MLP_IN], y[MLP_OUT];
     line_features(L, f);
@@ -329,18 +335,18 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) 
     if (!(x[0] == x[0] && x[1] == x[1] && x[2] == x[2] && x[3] == x[3])) {
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
     }
-  } else if (p.warm_start == 1 && active) {
+  } else if (START == START_PREV && active) {
     x[0] = s.vf[idx]; x[1] = s.vt[idx]; x[2] = s.thf[idx]; x[3] = s.tht[idx];
   } else {
     x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
   }
   if (active) {
     bool conv;
-    it = newton(L, lo, hi, x, p, n_eval, n_trial, n_cg, conv);
-    if (LEARNED && !conv) {
+    it = newton(L, lo, hi, x, p, n_eval, n_rej, n_cg, conv);
+    if (START == START_LEARNED && !conv) {
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton(L, lo, hi, x, p, n_eval, n_trial, n_cg, conv);
+      it += newton(L, lo, hi, x, p, n_eval, n_rej, n_cg, conv);
     }
     double S, C;
     sincos(x[2] - x[3], &S, &C);
@@ -366,7 +372,7 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) 
     }
   }
   // work counters: one wave-level sum and one atomic per wave and counter
-  unsigned long long c[5] = {(unsigned long long)n_eval, (unsigned long long)n_trial, (unsigned long long)n_cg,
+  unsigned long long c[5] = {(unsigned long long)n_eval, (unsigned long long)n_rej, (unsigned long long)n_cg,
                              (unsigned long long)it, (unsigned long long)n_fb};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -382,11 +388,14 @@ __global__ void __launch_bounds__(BLOCK) k_branch(Net n, State s, Par p, Mlp w) 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TL = n.T * n.L;
   if (TL == 0) return;
-  if (p.warm_start == 2) {
+  const dim3 grid((TL + BLOCK - 1) / BLOCK);
+  if (p.warm_start == START_LEARNED) {
     const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
-    hipLaunchKernelGGL(k_branch<true>, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), lds, st, n, s, p, p.mlp);
+    hipLaunchKernelGGL(k_branch<START_LEARNED>, grid, dim3(BLOCK), lds, st, n, s, p, p.mlp);
+  } else if (p.warm_start == START_PREV) {
+    hipLaunchKernelGGL(k_branch<START_PREV>, grid, dim3(BLOCK), 0, st, n, s, p, p.mlp);
   } else {
-    hipLaunchKernelGGL(k_branch<false>, dim3((TL + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p, p.mlp);
+    hipLaunchKernelGGL(k_branch<START_FLAT>, grid, dim3(BLOCK), 0, st, n, s, p, p.mlp);
   }
 }
 

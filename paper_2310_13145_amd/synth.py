@@ -152,6 +152,14 @@ def config_instance(cfg_id: int, instance: int = 0):
                          ring=(cfg_id == 0))
 
 
+def training_instance(cfg_id: int, k: int):
+    """Instance k of the same shape and distributions as workload cfg_id, drawn from a
+    seed that no evaluation workload uses (training data for the learned start)."""
+    c = CONFIGS[cfg_id]
+    return make_instance(c["n_bus"], c["n_line"], c["n_gen"], c["T"], SEED_BASE + 100_000 + 1000 * cfg_id + k,
+                         ring=(cfg_id == 0))
+
+
 def batch_member(k: int):
     """Member k of the uneven 64-instance batch: N ~ logU[30, 2000], L = round(1.5 N),
     G = round(0.25 N), T uniform in {12, 24, 48}."""
