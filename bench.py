@@ -51,9 +51,9 @@ BYTES_BUS_PER_END = 8 * 28  # per incident line end; plus per unit 24 and per bu
 # mesh2000_T24 bench command), each scaled by the ratio of true to counted bytes of a
 # plain copy kernel of known size.  They describe the kernel source they were taken
 # on (hash below) and are reported as null once that source has changed.
-BRANCH_COUNTERS = {"source_sha256": "bc3a6d8222698e5d9c67525fe5bef3fa9ab77a98688bb7f84a96fa8e645ef9ca",
-                   "fetch_kib": 7879.05, "write_kib": 6450.0, "fetch_scale": 2.0, "write_scale": 1.0}
-BRANCH_SOURCES = ("k_branch.hip", "ucac_dev.hpp", "ucac_mlp.hpp", "ucac_launch.hpp")
+BRANCH_COUNTERS = {"source_sha256": "b3d66fca26186613981a494c0423ed453b74a8efc9276995ed5ac6d16c0243c2",
+                   "fetch_kib": 7881.39, "write_kib": 6450.00, "fetch_scale": 2.0, "write_scale": 1.0}
+BRANCH_SOURCES = ("k_branch.hip", "ucac_mlp.hpp")  # the line kernel's own code
 
 
 def branch_source_hash():
@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--learned-steps", type=int, default=200)
     ap.add_argument("--learned-max-iters", type=int, default=4000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--batch-steps", type=int, default=100)
     return ap.parse_args()
 
 
@@ -214,6 +216,30 @@ def learned_start(ucac, synth, torch, args):
     return out
 
 
+def batching(ucac, synth, torch, args):
+    """64 independent instances of uneven size (30 to 2000 buses, T in {12, 24, 48}):
+    one grouped launch per kernel with the tuned mapping, against running the same
+    instances one at a time (each with its own captured graph)."""
+    insts = synth.batch_instances(64)
+    solves = sum(i["n_line"] * i["T"] for i in insts)
+    b = ucac.Batch(insts)
+    chosen, cand = b.autotune(iters=10)
+    sec = _timed_steps(b, torch, 10, args.batch_steps)
+    b.close()
+    seq = 0.0
+    for inst in insts:
+        s = ucac.Solver(inst)
+        seq += _timed_steps(s, torch, 10, args.batch_steps)
+        s.close()
+    return {"instances": len(insts), "buses": sum(i["n_bus"] for i in insts),
+            "branch_solves_per_iter": solves, "tuned_mapping": {"dp_lanes": chosen[0], "branch_block": chosen[1],
+                                                                "order": ["given", "largest_first"][chosen[2]]},
+            "candidates_ms_per_iter": {f"dp{k[0]}_bb{k[1]}_o{k[2]}": v for k, v in cand.items()},
+            "batched": {"ms_per_iter": 1e3 * sec, "branch_solves_per_s": solves / sec},
+            "one_at_a_time": {"ms_per_iter": 1e3 * seq, "branch_solves_per_s": solves / seq},
+            "speedup": seq / sec}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -306,6 +332,9 @@ def main():
     if not args.no_solve:
         out["time_to_tol"] = time_to_tol(ucac, torch, inst, args)
         out["time_to_tol_mesh118_T24"] = time_to_tol(ucac, torch, synth.config_instance(1), args)
+
+    if not args.no_batch:
+        out["batching"] = batching(ucac, synth, torch, args)
 
     if not args.no_learned:
         out["learned_start"] = learned_start(ucac, synth, torch, args)

@@ -214,6 +214,50 @@ int ucac_mlp_train(ucac_mlp* m, const float* x, const float* t, int64_t n, int32
 const char* ucac_mlp_last_error(const ucac_mlp* m);
 void ucac_mlp_destroy(ucac_mlp* m);
 
+/* ---- batches: many independent instances in one launch per kernel -----------
+ * Every member is an ordinary instance (its own arena and state), created from
+ * its network with the shared params.  One captured graph per iteration launches
+ * each kernel once for all members: the grid is the concatenation of the
+ * members' own grids and each block finds its member from small device tables.
+ * Each member keeps its own control (residuals, beta, lambda, convergence); in
+ * ucac_batch_solve a converged member stops (its blocks return at entry) while
+ * the others continue.  Members' iterates are bit-identical to what the same
+ * member would compute alone.  Not thread-safe; calls are serialized on the
+ * batch's stream. */
+typedef struct ucac_batch ucac_batch;
+
+/* Mapping choices (results do not depend on them):
+ *   dp_lanes      lanes per generator of the UC dynamic program: 64 (one
+ *                 wavefront per unit) or 16 (four units per wavefront);
+ *   branch_block  block size of the line kernel: 256 or 64;
+ *   order         0: members in the given order; 1: largest line work first. */
+typedef struct {
+  int32_t dp_lanes, branch_block, order;
+} ucac_batch_config;
+
+/* nets[n] (host, read during the call); params->warm_start must be 0 or 1.
+ * Errors of member k are reported as "member k: ..." by ucac_last_error(NULL). */
+int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* params, ucac_batch** out);
+int32_t ucac_batch_size(const ucac_batch* b);
+/* The member's handle, owned by the batch (do not destroy it): use it with
+ * ucac_residuals, ucac_get_solution, ucac_get_state, ucac_set_state. */
+int ucac_batch_member(ucac_batch* b, int32_t k, ucac_handle** member);
+/* n_iters inner iterations of every member. */
+int ucac_batch_step(ucac_batch* b, int32_t n_iters);
+/* Until every member has r_p, r_d <= tol or max_iters iterations; iters_done[n]
+ * and converged[n] (host, may be NULL) per member.  UCAC_OK when all converged,
+ * else UCAC_NOT_CONVERGED. */
+int ucac_batch_solve(ucac_batch* b, double tol, int32_t max_iters, int32_t* iters_done, int32_t* converged);
+/* Time every mapping candidate over `iters` iterations (plus 2 warm-up) from the
+ * current iterate, keep the fastest, and restore the iterate.  ms_per_iter
+ * receives up to n_slots per-candidate times (candidate order: dp_lanes
+ * {64,16} fastest-varying, then branch_block {256,64}, then order {0,1}). */
+int ucac_batch_autotune(ucac_batch* b, int32_t iters, ucac_batch_config* chosen, double* ms_per_iter, int32_t n_slots);
+int ucac_batch_set_config(ucac_batch* b, const ucac_batch_config* c);
+int ucac_batch_get_config(const ucac_batch* b, ucac_batch_config* c);
+const char* ucac_batch_last_error(const ucac_batch* b);
+void ucac_batch_destroy(ucac_batch* b);
+
 /* Message of the last error on this handle (or of the last failed create when
  * h is NULL).  Valid until the next call on the handle. */
 const char* ucac_last_error(const ucac_handle* h);

@@ -17,10 +17,10 @@
 
 namespace ucac {
 
-__global__ void __launch_bounds__(BLOCK) k_ubar(Net n, State s, Par p) {
+__device__ __forceinline__ void ubar_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int G = n.G, T = n.T, TG = T * G;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = blk * BLOCK + threadIdx.x;
   double dmax = 0.0;
   if (i < TG) {
     const int t = i / G, g = i - t * G;
@@ -106,6 +106,15 @@ __global__ void __launch_bounds__(BLOCK) k_ubar(Net n, State s, Par p) {
   block_max_to_ctl<1>(v, slot, s.ctl);
 }
 
+__global__ void __launch_bounds__(BLOCK) k_ubar(Net n, State s, Par p) { ubar_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_ubar_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  ubar_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+}
+
 __device__ inline void zy_update(double* zr, double* yr, const double* lr, int k, double a, double rho, double beta,
                                  double& rp, double& rin, double& zinf) {
   const double z = -(lr[k] + yr[k] + rho * a) / (beta + rho);
@@ -141,11 +150,11 @@ __device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, 
   return d;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) {
+__device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
   const int TL = T * n.L, TG = T * G;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const int idx = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
     const int t = idx / N, i = idx - t * N;
@@ -277,10 +286,19 @@ __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) {
   block_max_to_ctl<4>(v, slot, s.ctl);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) {
+__global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  bus_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+}
+
+__device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int G = n.G, TG = n.T * G;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, zinf = 0.0;
   if (i < TG) {
     const int t = i / G, g = i - t * G;
@@ -315,6 +333,29 @@ __global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) {
   const double v[3] = {rp, rin, zinf};
   const int slot[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
   block_max_to_ctl<3>(v, slot, s.ctl);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_gen_dual_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  gen_dual_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+}
+
+int ubar_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
+int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+
+void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(BLOCK), 0, st, g);
+}
+void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
+}
+void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {

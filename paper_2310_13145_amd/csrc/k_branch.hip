@@ -294,11 +294,11 @@ __device__ inline void encode_solution(const Line& L, const double (&x)[4], floa
 // of the others' code and registers.
 enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
 
-template <int START>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_branch(Net n, State s, Par p, Mlp w) {
+template <int START, int BS>
+__device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
   if (s.ctl->halt) return;
   const int TL = n.T * n.L;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const int idx = blk * BS + threadIdx.x;
   const bool active = idx < TL;
   int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0;
   Line L = {};
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     extern __shared__ __bf16 lds_branch[];
     float f[MLP_IN], y[MLP_OUT];
     line_features(L, f);
-    mlp_forward_wave(w, f, lds_branch + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
+    mlp_forward_wave(p.mlp, f, lds_branch + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
     x[0] = 1.0 + (double)y[0];
     x[1] = 1.0 + (double)y[1];
     x[2] = L.c[6] + 0.1 * (double)y[2];
@@ -385,18 +385,47 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
   }
 }
 
-void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  const int TL = n.T * n.L;
-  if (TL == 0) return;
-  const dim3 grid((TL + BLOCK - 1) / BLOCK);
-  if (p.warm_start == START_LEARNED) {
-    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
-    hipLaunchKernelGGL(k_branch<START_LEARNED>, grid, dim3(BLOCK), lds, st, n, s, p, p.mlp);
-  } else if (p.warm_start == START_PREV) {
-    hipLaunchKernelGGL(k_branch<START_PREV>, grid, dim3(BLOCK), 0, st, n, s, p, p.mlp);
+template <int START, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_branch(Net n, State s, Par p) {
+  branch_body<START, BS>(n, s, p, blockIdx.x);
+}
+
+template <int START, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_branch_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  branch_body<START, BS>(M.n, M.s, M.p, blockIdx.x - gr.blk_first[mk]);
+}
+
+int branch_blocks(const Net& n, int block) { return (n.T * n.L + block - 1) / block; }
+
+template <int BS>
+static void launch_branch_bs(const Net* n, const State* s, const Par& p, const Group* g, int grid, int start, hipStream_t st) {
+  const size_t lds = start == START_LEARNED ? sizeof(__bf16) * MLP_WAVE_LDS * (BS / 64) : 0;
+  if (g) {
+    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch_group<START_LEARNED, BS>), dim3(grid), dim3(BS), lds, st, *g);
+    else if (start == START_PREV) hipLaunchKernelGGL((k_branch_group<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *g);
+    else hipLaunchKernelGGL((k_branch_group<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *g);
   } else {
-    hipLaunchKernelGGL(k_branch<START_FLAT>, grid, dim3(BLOCK), 0, st, n, s, p, p.mlp);
+    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch<START_LEARNED, BS>), dim3(grid), dim3(BS), lds, st, *n, *s, p);
+    else if (start == START_PREV) hipLaunchKernelGGL((k_branch<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
+    else hipLaunchKernelGGL((k_branch<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
   }
+}
+
+void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block) {
+  if (n.T * n.L == 0) return;
+  const int grid = branch_blocks(n, block);
+  if (block == 64) launch_branch_bs<64>(&n, &s, p, nullptr, grid, p.warm_start, st);
+  else launch_branch_bs<256>(&n, &s, p, nullptr, grid, p.warm_start, st);
+}
+
+void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_branch_block(n, s, p, st, 256); }
+
+void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st) {
+  const Par dummy{};
+  if (block == 64) launch_branch_bs<64>(nullptr, nullptr, dummy, &g, grid, warm_start, st);
+  else launch_branch_bs<256>(nullptr, nullptr, dummy, &g, grid, warm_start, st);
 }
 
 }  // namespace ucac

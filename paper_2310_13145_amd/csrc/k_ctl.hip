@@ -10,7 +10,7 @@
 
 namespace ucac {
 
-__global__ void k_finalize(Net n, State s, Par p) {
+__device__ __forceinline__ void finalize_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   Ctl* c = s.ctl;
   if (c->halt) return;
   if (threadIdx.x != 0) return;
@@ -48,28 +48,57 @@ __global__ void k_finalize(Net n, State s, Par p) {
   }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_lambda(Net n, State s, Par p) {
+__global__ void k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void k_finalize_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  finalize_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+}
+
+__device__ __forceinline__ void lambda_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   const Ctl* c = s.ctl;
   if (c->halt || !c->pending) return;
   const int TL = n.T * n.L, TG = n.T * n.G;
   const int nb = NRB * TL, total = nb + NRG * TG;
   const double b = c->beta_for_lambda, lm = p.lambda_max;
-  for (int k = blockIdx.x * BLOCK + threadIdx.x; k < total; k += gridDim.x * BLOCK) {
+  for (int k = blk * BLOCK + threadIdx.x; k < total; k += nblk * BLOCK) {
     if (k < nb) s.lB[k] = clampd(s.lB[k] + b * s.zB[k], -lm, lm);
     else s.lG[k - nb] = clampd(s.lG[k - nb] + b * s.zG[k - nb], -lm, lm);
   }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_lambda(Net n, State s, Par p) { lambda_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_lambda_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  lambda_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, n, s, p);
 }
 
-void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st) {
+int lambda_blocks(const Net& n) {
   const long total = (long)NRB * n.T * n.L + (long)NRG * n.T * n.G;
   long blocks = (total + BLOCK - 1) / BLOCK;
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_lambda, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, s, p);
+  return (int)blocks;
+}
+
+void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_lambda, dim3(lambda_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
+}
+
+void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(64), 0, st, g);
+}
+void launch_lambda_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_lambda_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 
 }  // namespace ucac

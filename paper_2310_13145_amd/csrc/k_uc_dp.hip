@@ -1,10 +1,11 @@
 // step:uc -- one dynamic program per generator (Sec. III-B, Alg. dp_algo).
 //
-// One 64-lane wavefront per generator.  The lanes build the cost table
+// A group of 64 or 16 lanes per generator (one wavefront per generator, or four
+// generators per wavefront).  The group's lanes build the cost table
 // L^UC_{g,t}(s', s) for all periods in parallel into LDS (4 doubles per period),
-// then lane 0 runs the backward stay/switch induction (keep_formula,
-// switch_formula) and the forward reconstruction from one decision bit per
-// (period, state) -- O(T) extra space instead of the paper's stored O(T^2)
+// then the group's first lane runs the backward stay/switch induction
+// (keep_formula, switch_formula) and the forward reconstruction from one decision
+// bit per (period, state) -- O(T) extra space instead of the paper's stored O(T^2)
 // trajectories -- and the lanes write u_on/u_su/u_sd back, one period each.
 //
 // This file is compiled with -ffp-contract=off: the table entries and the
@@ -31,32 +32,49 @@ __device__ inline double uc_table_entry(double cnl, double csu, double csd, doub
   return L;
 }
 
-__global__ void __launch_bounds__(64) k_uc_dp(Net n, State s, Par p) {
-  if (s.ctl->halt) return;
-  const int g = blockIdx.x;
-  const int T = n.T, G = n.G;
-  const int lane = threadIdx.x;
-  extern __shared__ double lds[];
-  double* Lt = lds;                       // [T][2][2]
-  double* c = Lt + 4 * T;                 // [T+2][2], c[T+1][*] = 0
-  unsigned char* dec = (unsigned char*)(c + 2 * (T + 2));  // [T+2][2]
-  signed char* u = (signed char*)(dec + 2 * (T + 2));     // [T]
+// LDS bytes of one generator's DP at horizon T: cost table [T][2][2], cost-to-go
+// [T+2][2], decision bits [T+2][2], schedule [T]; padded to 8 bytes.
+__host__ __device__ inline size_t dp_slot_bytes(int T) {
+  const size_t b = sizeof(double) * (4 * (size_t)T + 2 * ((size_t)T + 2)) + 2 * ((size_t)T + 2) + (size_t)T;
+  return (b + 7) & ~(size_t)7;
+}
 
-  const double cnl = n.cnl[g], csu = n.csu[g], csd = n.csd[g], rho = p.rho_uc;
+// LPG lanes per generator (64: one wavefront; 16: four generators per wavefront).
+// The LPG lanes of a generator build its table; the group's first lane runs the
+// recursion and the reconstruction.  slotT: horizon the LDS slots are sized for.
+template <int LPG>
+__device__ __forceinline__ void uc_dp_body(const Net& n, const State& s, const Par& p, int blk, int slotT) {
+  if (s.ctl->halt) return;
+  constexpr int GPB = 64 / LPG;  // generators per block
+  const int T = n.T, G = n.G;
+  const int sub = threadIdx.x / LPG, lane = threadIdx.x - sub * LPG;
+  const int g = blk * GPB + sub;
+  const bool act = g < G;
+  extern __shared__ double lds[];
+  char* base = (char*)lds + dp_slot_bytes(slotT) * sub;
+  double* Lt = (double*)base;              // [T][2][2]
+  double* c = Lt + 4 * T;                  // [T+2][2], c[T+1][*] = 0
+  unsigned char* dec = (unsigned char*)(c + 2 * (T + 2));  // [T+2][2]
+  signed char* u = (signed char*)(dec + 2 * (T + 2));      // [T]
+
+  const double rho = p.rho_uc;
   const int TGs = T * G;
-  for (int t = lane; t < T; t += 64) {
-    const int k = t * G + g;
-    const double ub[3] = {s.ubon[k], s.ubsu[k], s.ubsd[k]};
-    const double z[3] = {s.zG[RG_U1 * TGs + k], s.zG[RG_U2 * TGs + k], s.zG[RG_U3 * TGs + k]};
-    const double y[3] = {s.yG[RG_U1 * TGs + k], s.yG[RG_U2 * TGs + k], s.yG[RG_U3 * TGs + k]};
+  if (act) {
+    const double cnl = n.cnl[g], csu = n.csu[g], csd = n.csd[g];
+    for (int t = lane; t < T; t += LPG) {
+      const int k = t * G + g;
+      const double ub[3] = {s.ubon[k], s.ubsu[k], s.ubsd[k]};
+      const double z[3] = {s.zG[RG_U1 * TGs + k], s.zG[RG_U2 * TGs + k], s.zG[RG_U3 * TGs + k]};
+      const double y[3] = {s.yG[RG_U1 * TGs + k], s.yG[RG_U2 * TGs + k], s.yG[RG_U3 * TGs + k]};
 #pragma unroll
-    for (int sp = 0; sp < 2; ++sp)
+      for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-      for (int ss = 0; ss < 2; ++ss) Lt[(t * 2 + sp) * 2 + ss] = uc_table_entry(cnl, csu, csd, rho, sp, ss, ub, z, y);
+        for (int ss = 0; ss < 2; ++ss) Lt[(t * 2 + sp) * 2 + ss] = uc_table_entry(cnl, csu, csd, rho, sp, ss, ub, z, y);
+    }
   }
   __syncthreads();
 
-  if (lane == 0) {
+  if (act && lane == 0) {
     const int u0 = n.u0[g], TU = n.tu[g], TD = n.td[g];
     int hold = u0 ? n.lon[g] : n.loff[g];
     hold = hold > T ? T : (hold < 0 ? 0 : hold);
@@ -96,21 +114,50 @@ __global__ void __launch_bounds__(64) k_uc_dp(Net n, State s, Par p) {
   }
   __syncthreads();
 
-  const int u0 = n.u0[g];
-  for (int t = lane; t < T; t += 64) {
-    const int k = t * G + g;
-    const int cur = u[t];
-    const int prev = t == 0 ? u0 : u[t - 1];
-    s.uon[k] = (double)cur;
-    s.usu[k] = cur > prev ? 1.0 : 0.0;
-    s.usd[k] = prev > cur ? 1.0 : 0.0;
+  if (act) {
+    const int u0 = n.u0[g];
+    for (int t = lane; t < T; t += LPG) {
+      const int k = t * G + g;
+      const int cur = u[t];
+      const int prev = t == 0 ? u0 : u[t - 1];
+      s.uon[k] = (double)cur;
+      s.usu[k] = cur > prev ? 1.0 : 0.0;
+      s.usd[k] = prev > cur ? 1.0 : 0.0;
+    }
   }
 }
 
-void launch_uc_dp(const Net& n, const State& s, const Par& p, hipStream_t st) {
+template <int LPG>
+__global__ void __launch_bounds__(64) k_uc_dp(Net n, State s, Par p) {
+  uc_dp_body<LPG>(n, s, p, blockIdx.x, n.T);
+}
+
+template <int LPG>
+__global__ void __launch_bounds__(64) k_uc_dp_group(Group gr, int slotT) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  uc_dp_body<LPG>(M.n, M.s, M.p, blockIdx.x - gr.blk_first[mk], slotT);
+}
+
+int uc_dp_blocks(const Net& n, int dp_lanes) {
+  const int gpb = 64 / dp_lanes;
+  return (n.G + gpb - 1) / gpb;
+}
+
+void launch_uc_dp_lanes(const Net& n, const State& s, const Par& p, hipStream_t st, int dp_lanes) {
   if (n.G == 0) return;
-  const size_t lds = sizeof(double) * (4 * (size_t)n.T + 2 * ((size_t)n.T + 2)) + 2 * ((size_t)n.T + 2) + (size_t)n.T;
-  hipLaunchKernelGGL(k_uc_dp, dim3(n.G), dim3(64), lds, st, n, s, p);
+  const int nb = uc_dp_blocks(n, dp_lanes);
+  const size_t lds = dp_slot_bytes(n.T) * (64 / dp_lanes);
+  if (dp_lanes == 16) hipLaunchKernelGGL(k_uc_dp<16>, dim3(nb), dim3(64), lds, st, n, s, p);
+  else hipLaunchKernelGGL(k_uc_dp<64>, dim3(nb), dim3(64), lds, st, n, s, p);
+}
+
+void launch_uc_dp(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_uc_dp_lanes(n, s, p, st, 64); }
+
+void launch_uc_dp_grouped(const Group& g, int grid, int dp_lanes, int max_T, hipStream_t st) {
+  const size_t lds = dp_slot_bytes(max_T) * (64 / dp_lanes);
+  if (dp_lanes == 16) hipLaunchKernelGGL(k_uc_dp_group<16>, dim3(grid), dim3(64), lds, st, g, max_T);
+  else hipLaunchKernelGGL(k_uc_dp_group<64>, dim3(grid), dim3(64), lds, st, g, max_T);
 }
 
 }  // namespace ucac

@@ -1118,3 +1118,352 @@ void ucac_destroy(ucac_handle* h) {
 }
 
 }  // extern "C"
+
+// ---- batches: many independent instances, one grouped launch per kernel ----------
+
+struct ucac_batch {
+  int device = 0;
+  int warm_start = 0;
+  std::vector<ucac_handle*> m;
+  hipStream_t st = nullptr;
+  Member* d_members = nullptr;
+  int* d_tables = nullptr;       // per kernel: blk_member [grid], blk_first [n], blk_count [n]
+  Group grp[K_COUNT]{};
+  int grid[K_COUNT]{};
+  int max_T = 1;
+  ucac_batch_config cfg{64, 256, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> it0;
+  std::string err;
+};
+
+namespace {
+
+int bfail(ucac_batch* b, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf; else g_create_error = buf;
+  return code;
+}
+
+#define BHIP_OR(b, call)                                                                              \
+  do {                                                                                                \
+    hipError_t _e = (call);                                                                           \
+    if (_e != hipSuccess) return bfail(b, UCAC_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+int kernel_blocks(int k, const Net& n, const ucac_batch_config& c) {
+  switch (k) {
+    case K_UC_DP: return n.G ? uc_dp_blocks(n, c.dp_lanes) : 0;
+    case K_GEN: return gen_blocks(n);
+    case K_BRANCH: return branch_blocks(n, c.branch_block);
+    case K_UBAR: return ubar_blocks(n);
+    case K_BUS: return bus_blocks(n);
+    case K_GEN_DUAL: return gen_dual_blocks(n);
+    case K_FINALIZE: return 1;
+    default: return lambda_blocks(n);
+  }
+}
+
+// Block tables of every kernel for the configured member order, and the graph.
+int batch_build(ucac_batch* b) {
+  const int n = (int)b->m.size();
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  if (b->cfg.order == 1)  // largest line work first, so the longest blocks start first
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+      return (long)b->m[a]->T * b->m[a]->L > (long)b->m[c]->T * b->m[c]->L;
+    });
+  std::vector<int> tab;
+  size_t off[K_COUNT];
+  for (int k = 0; k < K_COUNT; ++k) {
+    std::vector<int> first(n, 0), count(n, 0), member;
+    for (int j : order) {
+      const int nb = kernel_blocks(k, b->m[j]->net, b->cfg);
+      first[j] = (int)member.size();
+      count[j] = nb;
+      for (int q = 0; q < nb; ++q) member.push_back(j);
+    }
+    b->grid[k] = (int)member.size();
+    off[k] = tab.size();
+    tab.insert(tab.end(), member.begin(), member.end());
+    tab.insert(tab.end(), first.begin(), first.end());
+    tab.insert(tab.end(), count.begin(), count.end());
+  }
+  if (b->d_tables) { (void)hipFree(b->d_tables); b->d_tables = nullptr; }
+  BHIP_OR(b, hipMalloc(&b->d_tables, sizeof(int) * tab.size()));
+  BHIP_OR(b, hipMemcpy(b->d_tables, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice));
+  for (int k = 0; k < K_COUNT; ++k) {
+    Group& g = b->grp[k];
+    g.m = b->d_members;
+    g.blk_member = b->d_tables + off[k];
+    g.blk_first = g.blk_member + b->grid[k];
+    g.blk_count = g.blk_first + n;
+  }
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  (void)hipGetLastError();
+  BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
+  hipError_t le = hipSuccess;
+  const char* where = "";
+  for (int k = 0; k < K_COUNT && le == hipSuccess; ++k) {
+    if (b->grid[k] == 0) continue;
+    const Group& g = b->grp[k];
+    switch (k) {
+      case K_UC_DP: launch_uc_dp_grouped(g, b->grid[k], b->cfg.dp_lanes, b->max_T, b->st); break;
+      case K_GEN: launch_gen_grouped(g, b->grid[k], b->st); break;
+      case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, b->st); break;
+      case K_UBAR: launch_ubar_grouped(g, b->grid[k], b->st); break;
+      case K_BUS: launch_bus_grouped(g, b->grid[k], b->st); break;
+      case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], b->st); break;
+      case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], b->st); break;
+      default: launch_lambda_grouped(g, b->grid[k], b->st); break;
+    }
+    le = hipGetLastError();
+    if (le != hipSuccess) where = names[k];
+  }
+  const hipError_t ce = hipStreamEndCapture(b->st, &b->graph);
+  if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
+  if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+  BHIP_OR(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return UCAC_OK;
+}
+
+int batch_set_ctl(ucac_batch* b, int stop_at_tol, double tol) {
+  for (ucac_handle* h : b->m) {
+    std::memset(h->h_ctl, 0, sizeof(Ctl));
+    h->h_ctl->stop_at_tol = stop_at_tol;
+    h->h_ctl->tol = tol;
+    const double ms[3] = {1e-2, 1e-3, 1e-4};
+    for (int q = 0; q < 3; ++q) { h->h_ctl->ms_tol[q] = ms[q]; h->h_ctl->ms_iter[q] = -1; }
+    BHIP_OR(b, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, b->st));
+  }
+  return UCAC_OK;
+}
+
+int batch_read(ucac_batch* b) {
+  for (ucac_handle* h : b->m) {
+    BHIP_OR(b, hipMemcpyAsync(h->h_sc, h->st.sc, sizeof(double) * NSC, hipMemcpyDeviceToHost, b->st));
+    BHIP_OR(b, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, b->st));
+  }
+  BHIP_OR(b, hipStreamSynchronize(b->st));
+  for (size_t k = 0; k < b->m.size(); ++k)
+    if (b->m[k]->h_ctl->bad) return bfail(b, UCAC_E_NUMERIC, "member %zu: non-finite residual in the iterate", k);
+  return UCAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* params, ucac_batch** out) {
+  if (!out) return bfail(nullptr, UCAC_E_INVAL, "null output handle");
+  *out = nullptr;
+  if (!nets || !params || n < 1) return bfail(nullptr, UCAC_E_INVAL, "need at least one network and params");
+  if (params->warm_start < 0 || params->warm_start > 1)
+    return bfail(nullptr, UCAC_E_INVAL, "batches take the flat (0) or previous-iterate (1) Newton start");
+  ucac_batch* b = new ucac_batch();
+  b->device = params->device;
+  b->warm_start = params->warm_start;
+  auto bad = [&](int code) {
+    const std::string e = g_create_error;
+    ucac_batch_destroy(b);
+    g_create_error = e;
+    return code;
+  };
+  for (int k = 0; k < n; ++k) {
+    ucac_handle* h = nullptr;
+    const int rc = ucac_create(&nets[k], params, &h);
+    if (rc != UCAC_OK) {
+      g_create_error = "member " + std::to_string(k) + ": " + g_create_error;
+      return bad(rc);
+    }
+    b->m.push_back(h);
+    b->max_T = std::max(b->max_T, h->T);
+  }
+  if (hipSetDevice(b->device) != hipSuccess) return bad(bfail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed"));
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess)
+    return bad(bfail(nullptr, UCAC_E_DEVICE, "stream create failed"));
+  std::vector<Member> hm(n);
+  for (int k = 0; k < n; ++k) hm[k] = Member{b->m[k]->net, b->m[k]->st, b->m[k]->kp};
+  if (hipMalloc(&b->d_members, sizeof(Member) * n) != hipSuccess ||
+      hipMemcpy(b->d_members, hm.data(), sizeof(Member) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return bad(bfail(nullptr, UCAC_E_NOMEM, "member table allocation failed"));
+  if (batch_build(b) != UCAC_OK) {
+    g_create_error = b->err;
+    return bad(UCAC_E_DEVICE);
+  }
+  *out = b;
+  return UCAC_OK;
+}
+
+int32_t ucac_batch_size(const ucac_batch* b) { return b ? (int32_t)b->m.size() : 0; }
+
+int ucac_batch_member(ucac_batch* b, int32_t k, ucac_handle** member) {
+  if (!b || !member) return UCAC_E_INVAL;
+  if (k < 0 || k >= (int32_t)b->m.size()) return bfail(b, UCAC_E_INVAL, "member %d out of range", k);
+  BHIP_OR(b, hipStreamSynchronize(b->st));
+  *member = b->m[k];
+  return UCAC_OK;
+}
+
+int ucac_batch_step(ucac_batch* b, int32_t n_iters) {
+  if (!b) return UCAC_E_INVAL;
+  if (n_iters < 0) return bfail(b, UCAC_E_INVAL, "negative iteration count");
+  BHIP_OR(b, hipSetDevice(b->device));
+  for (ucac_handle* h : b->m) BHIP_OR(b, hipStreamSynchronize(h->stream));
+  int rc = batch_set_ctl(b, 0, b->m[0]->par.tol);
+  if (rc) return rc;
+  for (int i = 0; i < n_iters; ++i) BHIP_OR(b, hipGraphLaunch(b->exec, b->st));
+  return batch_read(b);
+}
+
+int ucac_batch_solve(ucac_batch* b, double tol, int32_t max_iters, int32_t* iters_done, int32_t* converged) {
+  if (!b) return UCAC_E_INVAL;
+  if (!(tol > 0.0) || max_iters < 0) return bfail(b, UCAC_E_INVAL, "bad tol or max_iters");
+  BHIP_OR(b, hipSetDevice(b->device));
+  for (ucac_handle* h : b->m) BHIP_OR(b, hipStreamSynchronize(h->stream));
+  int rc = batch_read(b);
+  if (rc) return rc;
+  const int n = (int)b->m.size();
+  std::vector<double> it0(n);
+  for (int k = 0; k < n; ++k) {
+    ucac_handle* h = b->m[k];
+    h->par.tol = tol;
+    it0[k] = h->h_sc[SC_ITER];
+    h->h_sc[SC_CONV] = 0.0;
+    BHIP_OR(b, hipMemcpyAsync(h->st.sc + SC_CONV, h->h_sc + SC_CONV, sizeof(double), hipMemcpyHostToDevice, b->st));
+  }
+  rc = batch_set_ctl(b, 1, tol);
+  if (rc) return rc;
+  int launched = 0;
+  bool all = false;
+  while (!all && launched < max_iters) {
+    const int c = std::min(SOLVE_CHUNK, max_iters - launched);
+    for (int i = 0; i < c; ++i) BHIP_OR(b, hipGraphLaunch(b->exec, b->st));
+    launched += c;
+    rc = batch_read(b);
+    if (rc) return rc;
+    all = true;
+    for (ucac_handle* h : b->m) all = all && h->h_sc[SC_CONV] != 0.0;
+  }
+  int n_conv = 0;
+  for (int k = 0; k < n; ++k) {
+    const bool cv = b->m[k]->h_sc[SC_CONV] != 0.0;
+    n_conv += cv;
+    if (iters_done) iters_done[k] = (int32_t)(b->m[k]->h_sc[SC_ITER] - it0[k]);
+    if (converged) converged[k] = cv ? 1 : 0;
+  }
+  return n_conv == n ? UCAC_OK : UCAC_NOT_CONVERGED;
+}
+
+int ucac_batch_set_config(ucac_batch* b, const ucac_batch_config* c) {
+  if (!b || !c) return UCAC_E_INVAL;
+  if ((c->dp_lanes != 16 && c->dp_lanes != 64) || (c->branch_block != 64 && c->branch_block != 256) ||
+      (c->order != 0 && c->order != 1))
+    return bfail(b, UCAC_E_INVAL, "config: dp_lanes 16|64, branch_block 64|256, order 0|1");
+  BHIP_OR(b, hipSetDevice(b->device));
+  BHIP_OR(b, hipStreamSynchronize(b->st));
+  b->cfg = *c;
+  return batch_build(b);
+}
+
+int ucac_batch_get_config(const ucac_batch* b, ucac_batch_config* c) {
+  if (!b || !c) return UCAC_E_INVAL;
+  *c = b->cfg;
+  return UCAC_OK;
+}
+
+int ucac_batch_autotune(ucac_batch* b, int32_t iters, ucac_batch_config* chosen, double* ms_per_iter, int32_t n_slots) {
+  if (!b) return UCAC_E_INVAL;
+  if (iters < 1) return bfail(b, UCAC_E_INVAL, "iters must be positive");
+  BHIP_OR(b, hipSetDevice(b->device));
+  for (ucac_handle* h : b->m) BHIP_OR(b, hipStreamSynchronize(h->stream));
+  BHIP_OR(b, hipStreamSynchronize(b->st));
+  // every candidate runs from the same saved iterate, which is restored at the end
+  size_t total = 0;
+  for (ucac_handle* h : b->m) total += h->n_state;
+  double* save = nullptr;
+  BHIP_OR(b, hipMalloc(&save, sizeof(double) * total));
+  auto restore = [&]() -> hipError_t {
+    size_t o = 0;
+    for (ucac_handle* h : b->m) {
+      const hipError_t e = hipMemcpyAsync(h->d_state, save + o, sizeof(double) * h->n_state, hipMemcpyDeviceToDevice, b->st);
+      if (e != hipSuccess) return e;
+      o += h->n_state;
+    }
+    return hipStreamSynchronize(b->st);
+  };
+  {
+    size_t o = 0;
+    for (ucac_handle* h : b->m) {
+      if (hipMemcpyAsync(save + o, h->d_state, sizeof(double) * h->n_state, hipMemcpyDeviceToDevice, b->st) != hipSuccess) {
+        (void)hipFree(save);
+        return bfail(b, UCAC_E_DEVICE, "state save failed");
+      }
+      o += h->n_state;
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const ucac_batch_config cand[] = {{64, 256, 0}, {16, 256, 0}, {64, 64, 0}, {16, 64, 0},
+                                    {64, 256, 1}, {16, 256, 1}, {64, 64, 1}, {16, 64, 1}};
+  const int nc = (int)(sizeof cand / sizeof cand[0]);
+  double best = 1e300;
+  ucac_batch_config bestc = b->cfg;
+  int rc = UCAC_OK;
+  for (int c = 0; c < nc && rc == UCAC_OK; ++c) {
+    b->cfg = cand[c];
+    rc = batch_build(b);
+    if (rc) break;
+    if (restore() != hipSuccess) { rc = bfail(b, UCAC_E_DEVICE, "state restore failed"); break; }
+    rc = batch_set_ctl(b, 0, b->m[0]->par.tol);
+    if (rc) break;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, b->st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, b->st);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, b->st);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { rc = bfail(b, UCAC_E_DEVICE, "tuning run failed: %s", hipGetErrorString(e)); break; }
+    const double per = ms / iters;
+    if (ms_per_iter && c < n_slots) ms_per_iter[c] = per;
+    if (per < best) { best = per; bestc = cand[c]; }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc == UCAC_OK) {
+    b->cfg = bestc;
+    rc = batch_build(b);
+  }
+  if (rc == UCAC_OK && restore() != hipSuccess) rc = bfail(b, UCAC_E_DEVICE, "state restore failed");
+  (void)hipFree(save);
+  if (rc == UCAC_OK && chosen) *chosen = bestc;
+  if (rc == UCAC_OK) rc = batch_read(b);
+  return rc;
+}
+
+const char* ucac_batch_last_error(const ucac_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+void ucac_batch_destroy(ucac_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_tables) (void)hipFree(b->d_tables);
+  if (b->d_members) (void)hipFree(b->d_members);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  for (ucac_handle* h : b->m) ucac_destroy(h);
+  delete b;
+}
+
+}  // extern "C"

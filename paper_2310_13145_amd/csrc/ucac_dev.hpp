@@ -95,6 +95,26 @@ struct Par {
   MlpView mlp;
 };
 
+// ---- batched (grouped) launches ----------------------------------------------
+//
+// Many independent instances run through one launch per kernel: the grid is the
+// concatenation of every member's own grid (block ranges contiguous per member, in
+// the order the tuner chose), and each block finds its member and its block index
+// inside that member's grid from two small tables.  The kernel bodies are the
+// single-instance ones, unchanged.
+struct Member {
+  Net n;
+  State s;
+  Par p;
+};
+
+struct Group {
+  const Member* m;        // [members]
+  const int* blk_member;  // [grid] member of each block
+  const int* blk_first;   // [members] first block of each member's range
+  const int* blk_count;   // [members] blocks of each member's range
+};
+
 // ---- reductions -------------------------------------------------------------
 
 // max that keeps a NaN visible (fmax alone would drop it)

@@ -58,6 +58,12 @@ class ucac_params(C.Structure):
     ]
 
 
+class ucac_batch_config(C.Structure):
+    _fields_ = [("dp_lanes", C.c_int32), ("branch_block", C.c_int32), ("order", C.c_int32)]
+
+
+BATCH_CANDIDATES = [(dl, bb, od) for od in (0, 1) for bb in (256, 64) for dl in (64, 16)]
+
 _INT_FIELDS = {"line_from", "line_to", "gen_bus", "gen_min_up", "gen_min_dn", "gen_u0", "gen_init_on", "gen_init_off"}
 
 _lib = None
@@ -103,11 +109,26 @@ def lib():
         L.ucac_mlp_last_error.restype = C.c_char_p
         L.ucac_mlp_destroy.argtypes = [vp]
         L.ucac_mlp_destroy.restype = None
+        L.ucac_batch_create.argtypes = [C.POINTER(ucac_network), C.c_int32, C.POINTER(ucac_params), C.POINTER(vp)]
+        L.ucac_batch_size.argtypes = [vp]
+        L.ucac_batch_size.restype = C.c_int32
+        L.ucac_batch_member.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+        L.ucac_batch_step.argtypes = [vp, C.c_int32]
+        L.ucac_batch_solve.argtypes = [vp, C.c_double, C.c_int32, vp, vp]
+        L.ucac_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(ucac_batch_config), vp, C.c_int32]
+        L.ucac_batch_set_config.argtypes = [vp, C.POINTER(ucac_batch_config)]
+        L.ucac_batch_get_config.argtypes = [vp, C.POINTER(ucac_batch_config)]
+        L.ucac_batch_last_error.argtypes = [vp]
+        L.ucac_batch_last_error.restype = C.c_char_p
+        L.ucac_batch_destroy.argtypes = [vp]
+        L.ucac_batch_destroy.restype = None
         for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
                      "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
                      "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones",
                      "ucac_set_warmstart", "ucac_log_pairs", "ucac_mlp_create", "ucac_mlp_set_weights",
-                     "ucac_mlp_get_weights", "ucac_mlp_forward", "ucac_mlp_grad", "ucac_mlp_train"):
+                     "ucac_mlp_get_weights", "ucac_mlp_forward", "ucac_mlp_grad", "ucac_mlp_train",
+                     "ucac_batch_create", "ucac_batch_member", "ucac_batch_step", "ucac_batch_solve",
+                     "ucac_batch_autotune", "ucac_batch_set_config", "ucac_batch_get_config"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -414,3 +435,87 @@ class Solver:
         if cap is None:
             cap = n_iters * ((L * T + stride - 1) // stride)
         return ucac_log_pairs(self.h, n_iters, stride, cap)
+
+
+def _bcheck(rc, b, ok=(UCAC_OK,)):
+    if rc not in ok:
+        msg = lib().ucac_batch_last_error(b)
+        raise UcacError(rc, msg.decode() if msg else "")
+    return rc
+
+
+class Member(Solver):
+    """View of one member of a Batch (the batch owns the handle)."""
+
+    def __init__(self, batch, k):
+        inst = batch.insts[k]
+        self.inst = inst
+        self.params = batch.params
+        self.dims = (inst["n_bus"], inst["n_line"], inst["n_gen"], inst["T"])
+        h = C.c_void_p()
+        _bcheck(lib().ucac_batch_member(batch.b, int(k), C.byref(h)), batch.b)
+        self.h = h
+        self._batch = batch  # keeps the owner alive
+
+    def close(self):
+        self.h = None  # owned by the batch
+
+
+class Batch:
+    """Many independent instances advanced by one grouped launch per kernel."""
+
+    def __init__(self, insts, params: ucac_params | None = None, **over):
+        self.insts = list(insts)
+        self.params = params if params is not None else ucac_params_default(**over)
+        nets, self._keep = [], []
+        for inst in self.insts:
+            net, keep = make_network(inst)
+            nets.append(net)
+            self._keep.append(keep)
+        arr = (ucac_network * len(nets))(*nets)
+        b = C.c_void_p()
+        _bcheck(lib().ucac_batch_create(arr, len(nets), C.byref(self.params), C.byref(b)), None)
+        self.b = b
+
+    def __len__(self):
+        return len(self.insts)
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().ucac_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def member(self, k):
+        return Member(self, k)
+
+    def step(self, n=1):
+        _bcheck(lib().ucac_batch_step(self.b, int(n)), self.b)
+
+    def solve(self, tol=1e-4, max_iters=20000):
+        n = len(self.insts)
+        iters = np.zeros(n, dtype=np.int32)
+        conv = np.zeros(n, dtype=np.int32)
+        rc = _bcheck(lib().ucac_batch_solve(self.b, float(tol), int(max_iters), _ptr(iters), _ptr(conv)), self.b,
+                     ok=(UCAC_OK, UCAC_NOT_CONVERGED))
+        return rc, iters, conv.astype(bool)
+
+    def autotune(self, iters=10):
+        c = ucac_batch_config()
+        ms = np.zeros(len(BATCH_CANDIDATES))
+        _bcheck(lib().ucac_batch_autotune(self.b, int(iters), C.byref(c), _ptr(ms), len(ms)), self.b)
+        return (c.dp_lanes, c.branch_block, c.order), dict(zip(BATCH_CANDIDATES, ms.tolist()))
+
+    def set_config(self, dp_lanes=64, branch_block=256, order=0):
+        c = ucac_batch_config(dp_lanes, branch_block, order)
+        _bcheck(lib().ucac_batch_set_config(self.b, C.byref(c)), self.b)
+
+    def config(self):
+        c = ucac_batch_config()
+        _bcheck(lib().ucac_batch_get_config(self.b, C.byref(c)), self.b)
+        return (c.dp_lanes, c.branch_block, c.order)

@@ -89,3 +89,20 @@ def test_state_format_matches_oracle():
     inst = synth.config_instance(0)
     o = oracle.Oracle(inst)
     assert o.state_size() == sum(c for _, c in ucac.state_layout(9, 12, 3, 6))
+
+
+def test_batch_validation(lib):
+    """Batch arguments and member networks are checked before any device work."""
+    good = synth.small_instance(9, 12, 3, 6, seed=5)
+    bad = synth.small_instance(9, 12, 3, 6, seed=6)
+    bad["gen_pmin"] = bad["gen_pmax"] + 1.0
+    with pytest.raises(ucac.UcacError) as e:
+        ucac.Batch([bad, good])
+    assert e.value.code == ucac.UCAC_E_INVAL and "member 0" in str(e.value) and "pmin > pmax" in str(e.value)
+    with pytest.raises(ucac.UcacError) as e:
+        ucac.Batch([good], warm_start=2)
+    assert e.value.code == ucac.UCAC_E_INVAL
+    b = C.c_void_p()
+    p = ucac.ucac_params_default()
+    assert lib.ucac_batch_create(None, 0, C.byref(p), C.byref(b)) == ucac.UCAC_E_INVAL
+    assert ucac.BATCH_CANDIDATES[0] == (64, 256, 0) and len(ucac.BATCH_CANDIDATES) == 8
