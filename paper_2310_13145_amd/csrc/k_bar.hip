@@ -12,7 +12,7 @@
 //            each incident line end and G1, G2 of its generators.
 // k_gen_dual one lane per (g, t): z and y of rows C1..C6 and U1..U3, and commits
 //            the new relaxed commitments.
-// Each kernel folds its residual maxima into the control block.
+// Each kernel stores its blocks' residual maxima into per-block slots.
 #include "ucac_launch.hpp"
 
 namespace ucac {
@@ -102,8 +102,8 @@ __device__ __forceinline__ void ubar_body(const Net& n, const State& s, const Pa
     }
   }
   const double v[1] = {dmax};
-  const int slot[1] = {ACC_RD};
-  block_max_to_ctl<1>(v, slot, s.ctl);
+  const int which[1] = {ACC_RD};
+  block_max_store<1>(v, which, s.red + (size_t)(s.red_ubar + blk) * NACC);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_ubar(Net n, State s, Par p) { ubar_body(n, s, p, blockIdx.x, gridDim.x); }
@@ -282,8 +282,8 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     }
   }
   const double v[4] = {rp, rin, rd, zinf};
-  const int slot[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
-  block_max_to_ctl<4>(v, slot, s.ctl);
+  const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
+  block_max_store<4>(v, which, s.red + (size_t)(s.red_bus + blk) * NACC);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
@@ -331,8 +331,8 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
     s.ubsd[i] = usd;
   }
   const double v[3] = {rp, rin, zinf};
-  const int slot[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
-  block_max_to_ctl<3>(v, slot, s.ctl);
+  const int which[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
+  block_max_store<3>(v, which, s.red + (size_t)(s.red_gdual + blk) * NACC);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }

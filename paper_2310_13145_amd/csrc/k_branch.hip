@@ -12,7 +12,10 @@
 // gfx950 mapping: FP64 vector ALU bound.  All Newton state (x, gradient, the 10
 // distinct Hessian entries, CG vectors) lives in VGPRs; every loop over the four
 // variables is unrolled so no array is indexed dynamically; one sincos per
-// function evaluation.  The objective's Hessian is assembled from two per-end
+// function evaluation.  The kernel is latency-bound (few wavefronts per SIMD, long
+// dependent FP64 chains), so sums are formed as trees, the CG quotients use a
+// refined hardware reciprocal, and sin/cos of the small angle difference come from
+// a short polynomial chain.  The objective's Hessian is assembled from two per-end
 // Gauss-Newton blocks and one weighted second-derivative block (all four flows
 // share the form a v_i^2 + b v_j^2 + v_i v_j (al cos d + be sin d)), so a full
 // evaluation costs about 200 flops.
@@ -38,6 +41,38 @@ struct Sym4 {
   double h00, h01, h02, h03, h11, h12, h13, h22, h23, h33;
 };
 
+// Quotient n / d for d > 0 from the hardware reciprocal refined by two Newton
+// steps (relative error within a few ulp; a shorter dependency chain than the
+// IEEE division sequence).  Used on the CG recurrences, where only the accuracy
+// matters.
+__device__ inline double qdiv(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return n * r;
+}
+
+// sin and cos of the angle difference.  For |x| <= pi/4 (the usual case: the two
+// end angles of a line stay close) both come from their Taylor series to degree
+// 17 / 16 (first omitted terms below 1e-17 relative), evaluated in x^2 by Estrin's
+// scheme so the dependency chain is five operations deep; larger angles use the
+// library routine.
+__device__ inline void sincos_line(double x, double& S, double& C) {
+  if (!(fabs(x) <= 0.78539816339744831)) {
+    sincos(x, &S, &C);
+    return;
+  }
+  const double y = x * x, y2 = y * y, y4 = y2 * y2;
+  // coefficients (-1)^k / (2k+1)! and (-1)^k / (2k)!, k = 0..8
+  double lo = fma(fma(-0.0001984126984126984, y, 0.008333333333333333), y2, fma(-0.16666666666666666, y, 1.0));
+  double hi = fma(fma(-7.647163731819816e-13, y, 1.6059043836821613e-10), y2,
+                  fma(-2.505210838544172e-08, y, 2.7557319223985893e-06));
+  S = x * fma(fma(2.8114572543455206e-15, y4, hi), y4, lo);
+  lo = fma(fma(-0.001388888888888889, y, 0.041666666666666664), y2, fma(-0.5, y, 1.0));
+  hi = fma(fma(-1.1470745597729725e-11, y, 2.08767569878681e-09), y2, fma(-2.755731922398589e-07, y, 2.48015873015873e-05));
+  C = fma(fma(4.779477332387385e-14, y4, hi), y4, lo);
+}
+
 __device__ inline void flows4(const Line& L, double vi, double vj, double C, double S, double& f0, double& f1,
                               double& f2, double& f3) {
   const double vv = vi * vj, vi2 = vi * vi, vj2 = vj * vj;
@@ -57,7 +92,7 @@ __device__ inline void rank1(Sym4& H, double w, const double (&v)[4]) {
 __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&g)[4], Sym4& H) {
   const double vi = x[0], vj = x[1];
   double S, C;
-  sincos(x[2] - x[3], &S, &C);
+  sincos_line(x[2] - x[3], S, C);
   const double vv = vi * vj;
   // per-flow (a, b, al, be)
   const double a[4] = {L.G, -L.Bs, 0.0, 0.0};
@@ -108,7 +143,7 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
     Tdw += w[k] * Td[k];
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) g[i] = w[0] * gf[0][i] + w[1] * gf[1][i] + w[2] * gf[2][i] + w[3] * gf[3][i];
+  for (int i = 0; i < 4; ++i) g[i] = (w[0] * gf[0][i] + w[1] * gf[1][i]) + (w[2] * gf[2][i] + w[3] * gf[3][i]);
   // weighted second derivatives of the flows
   H.h00 += 2.0 * Aw;      H.h01 += Tw;           H.h02 += vj * Tdw;  H.h03 -= vj * Tdw;
   H.h11 += 2.0 * Bw;      H.h12 += vi * Tdw;     H.h13 -= vi * Tdw;
@@ -128,15 +163,16 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
   return F;
 }
 
+// 4-term sums are formed as two pairs (a tree): a shorter dependency chain.
 __device__ inline void symv(const Sym4& H, const double (&v)[4], double (&out)[4]) {
-  out[0] = H.h00 * v[0] + H.h01 * v[1] + H.h02 * v[2] + H.h03 * v[3];
-  out[1] = H.h01 * v[0] + H.h11 * v[1] + H.h12 * v[2] + H.h13 * v[3];
-  out[2] = H.h02 * v[0] + H.h12 * v[1] + H.h22 * v[2] + H.h23 * v[3];
-  out[3] = H.h03 * v[0] + H.h13 * v[1] + H.h23 * v[2] + H.h33 * v[3];
+  out[0] = (H.h00 * v[0] + H.h01 * v[1]) + (H.h02 * v[2] + H.h03 * v[3]);
+  out[1] = (H.h01 * v[0] + H.h11 * v[1]) + (H.h12 * v[2] + H.h13 * v[3]);
+  out[2] = (H.h02 * v[0] + H.h12 * v[1]) + (H.h22 * v[2] + H.h23 * v[3]);
+  out[3] = (H.h03 * v[0] + H.h13 * v[1]) + (H.h23 * v[2] + H.h33 * v[3]);
 }
 
 __device__ inline double dot(const double (&a)[4], const double (&b)[4]) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+  return (a[0] * b[0] + a[1] * b[1]) + (a[2] * b[2] + a[3] * b[3]);
 }
 
 // Steihaug-Toint CG on the free variables (mask fr), radius delta.
@@ -154,7 +190,7 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
     for (int i = 0; i < 4; ++i) Hd[i] *= fr[i];
     const double dHd = dot(d, Hd);
     double zn[4];
-    const double alpha = rr / dHd;
+    const double alpha = qdiv(rr, dHd);  // used only when dHd > 0
 #pragma unroll
     for (int i = 0; i < 4; ++i) zn[i] = z[i] + alpha * d[i];
     if (dHd <= 0.0 || dot(zn, zn) >= delta2) {
@@ -169,7 +205,7 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
     for (int i = 0; i < 4; ++i) { r[i] += alpha * Hd[i]; z[i] = zn[i]; }
     const double rr_new = dot(r, r);
     if (rr_new <= tol2) break;
-    const double beta = rr_new / rr;
+    const double beta = qdiv(rr_new, rr);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = -r[i] + beta * d[i];
     rr = rr_new;
@@ -286,25 +322,15 @@ __device__ inline void encode_solution(const Line& L, const double (&x)[4], floa
 
 }  // namespace
 
-// Newton start: START_FLAT (mid-box voltages, zero angles), START_PREV (the line's
-// previous solution) or START_LEARNED: every wavefront first evaluates the warm-start
-// network for its 64 lines (BF16 MFMA, LDS staging) and starts Newton there; a lane
-// whose Newton does not reach the tolerance restarts from the flat start (the plain
-// method is the fallback).  One instantiation per start keeps the plain kernel free
-// of the others' code and registers.
-enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
-
-template <int START, int BS>
-__device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
-  if (s.ctl->halt) return;
-  const int TL = n.T * n.L;
-  const int idx = blk * BS + threadIdx.x;
-  const bool active = idx < TL;
-  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0;
+// The line subproblem of lane idx: admittances, rating, voltage boxes, line-limit
+// multipliers and the completed-square targets c_r = xbar_r - z_r - y_r / rho_r of
+// its eight rows.  Inactive lanes get a harmless unit line.
+__device__ __forceinline__ Line load_line(const Net& n, const State& s, const Par& p, int idx, bool active) {
   Line L = {};
   L.rate = 1.0; L.rate2 = 1.0;
   L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu; L.inv2mu = 0.5 / p.mu;  // uniform: scalar registers
   if (active) {
+    const int TL = n.T * n.L;
     const int t = idx / n.L, l = idx - t * n.L;
     const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
     L.G = n.adm[0 * n.L + l]; L.Bs = n.adm[1 * n.L + l]; L.Bm = n.adm[3 * n.L + l];
@@ -320,18 +346,31 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
       L.c[r] = xb[r] - s.zB[r * TL + idx] - s.yB[r * TL + idx] / rho;
     }
   }
+  return L;
+}
+
+// Newton start: START_FLAT (mid-box voltages, zero angles), START_PREV (the line's
+// previous solution) or START_LEARNED: the point k_line_start predicted; a lane whose
+// Newton does not reach the tolerance from there restarts from the flat start (the
+// plain method is the fallback).  One instantiation per start keeps the plain kernel
+// free of the others' code and registers.
+enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
+
+template <int START, int BS>
+__device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
+  if (s.ctl->halt) return;
+  const int TL = n.T * n.L;
+  const int idx = blk * BS + threadIdx.x;
+  const bool active = idx < TL;
+  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0;
+  const Line L = load_line(n, s, p, idx, active);
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
   double x[4];
-  if constexpr (START == START_LEARNED) {
-    extern __shared__ __bf16 lds_branch[];
-    float f[MLP_IN], y[MLP_OUT];
-    line_features(L, f);
-    mlp_forward_wave(p.mlp, f, lds_branch + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
-    x[0] = 1.0 + (double)y[0];
-    x[1] = 1.0 + (double)y[1];
-    x[2] = L.c[6] + 0.1 * (double)y[2];
-    x[3] = L.c[7] + 0.1 * (double)y[3];
+  if (START == START_LEARNED && active) {
+    // the point k_line_start predicted for this line (FP32), NaN-guarded
+    x[0] = (double)s.x0[idx]; x[1] = (double)s.x0[TL + idx];
+    x[2] = (double)s.x0[2 * TL + idx]; x[3] = (double)s.x0[3 * TL + idx];
     if (!(x[0] == x[0] && x[1] == x[1] && x[2] == x[2] && x[3] == x[3])) {
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
     }
@@ -371,7 +410,7 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
       }
     }
   }
-  // work counters: one wave-level sum and one atomic per wave and counter
+  // work counters: one wave-level sum per counter, added to the wave's own slot
   unsigned long long c[5] = {(unsigned long long)n_eval, (unsigned long long)n_rej, (unsigned long long)n_cg,
                              (unsigned long long)it, (unsigned long long)n_fb};
 #pragma unroll
@@ -380,8 +419,10 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
     for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
+    // this wavefront's own slot (no atomics: the same wave owns it in every launch)
+    unsigned long long* slot = s.br_count + (size_t)((blk * BS + (int)threadIdx.x) >> 6) * 5;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) atomicAdd(&s.br_count[k], c[k]);
+    for (int k = 0; k < 5; ++k) slot[k] += c[k];
   }
 }
 
@@ -397,17 +438,40 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_
   branch_body<START, BS>(M.n, M.s, M.p, blockIdx.x - gr.blk_first[mk]);
 }
 
+// Learned start, run just before the line kernel: every wavefront evaluates the
+// warm-start network on its 64 lines (20 local inputs each; BF16 MFMA, FP32
+// accumulation, activations in LDS) and stores the decoded start point
+// (v_i, v_j, th_i, th_j) as FP32 in x0 [4][T*L].  A kernel of its own so that the
+// Newton kernel keeps its registers (no spills) and the network runs at the
+// occupancy its small footprint allows.
+__global__ void __launch_bounds__(BLOCK) k_line_start(Net n, State s, Par p) {
+  if (s.ctl->halt) return;
+  extern __shared__ __bf16 lds_start[];
+  const int TL = n.T * n.L;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const bool active = idx < TL;
+  const Line L = load_line(n, s, p, idx, active);
+  float f[MLP_IN], y[MLP_OUT];
+  line_features(L, f);
+  mlp_forward_wave(p.mlp, f, lds_start + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
+  if (active) {
+    s.x0[idx] = 1.0f + y[0];
+    s.x0[TL + idx] = 1.0f + y[1];
+    s.x0[2 * TL + idx] = (float)(L.c[6] + 0.1 * (double)y[2]);
+    s.x0[3 * TL + idx] = (float)(L.c[7] + 0.1 * (double)y[3]);
+  }
+}
+
 int branch_blocks(const Net& n, int block) { return (n.T * n.L + block - 1) / block; }
 
 template <int BS>
 static void launch_branch_bs(const Net* n, const State* s, const Par& p, const Group* g, int grid, int start, hipStream_t st) {
-  const size_t lds = start == START_LEARNED ? sizeof(__bf16) * MLP_WAVE_LDS * (BS / 64) : 0;
   if (g) {
-    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch_group<START_LEARNED, BS>), dim3(grid), dim3(BS), lds, st, *g);
+    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch_group<START_LEARNED, BS>), dim3(grid), dim3(BS), 0, st, *g);
     else if (start == START_PREV) hipLaunchKernelGGL((k_branch_group<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *g);
     else hipLaunchKernelGGL((k_branch_group<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *g);
   } else {
-    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch<START_LEARNED, BS>), dim3(grid), dim3(BS), lds, st, *n, *s, p);
+    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch<START_LEARNED, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
     else if (start == START_PREV) hipLaunchKernelGGL((k_branch<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
     else hipLaunchKernelGGL((k_branch<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
   }
@@ -415,6 +479,10 @@ static void launch_branch_bs(const Net* n, const State* s, const Par& p, const G
 
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block) {
   if (n.T * n.L == 0) return;
+  if (p.warm_start == START_LEARNED) {
+    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
+    hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
+  }
   const int grid = branch_blocks(n, block);
   if (block == 64) launch_branch_bs<64>(&n, &s, p, nullptr, grid, p.warm_start, st);
   else launch_branch_bs<256>(&n, &s, p, nullptr, grid, p.warm_start, st);

@@ -1,6 +1,6 @@
 // Inner/outer control of the two-level ADMM, decided on the device.
 //
-// k_finalize reads the four residual maxima, clears the accumulators, advances
+// k_finalize reduces the four residual maxima from the per-block slots, advances
 // the counters and decides: converged (solve mode: r_p <= tol and r_d <= tol,
 // then every later kernel of the handle returns at entry), or end of the inner
 // loop (max(r_in, r_d) <= max(tol/2, eps_in0 2^-k), or max_inner iterations),
@@ -13,13 +13,28 @@ namespace ucac {
 __device__ __forceinline__ void finalize_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   Ctl* c = s.ctl;
   if (c->halt) return;
+  // reduce the per-block maxima of this iteration's kernels
+  double m[NACC] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < s.red_n; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) m[k] = nmax(m[k], s.red[(size_t)b * NACC + k]);
+  }
+  __shared__ double part[NACC][BLOCK / 64];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) m[k] = wave_max(m[k]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) part[k][threadIdx.x >> 6] = m[k];
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m[k] = nmax(m[k], part[k][w]);
+    m[k] = nmax(m[k], part[k][0]);
+  }
   double* sc = s.sc;
-  const double rp = __longlong_as_double((long long)c->acc[ACC_RP]);
-  const double rin = __longlong_as_double((long long)c->acc[ACC_RIN]);
-  const double rd = __longlong_as_double((long long)c->acc[ACC_RD]);
-  const double zinf = __longlong_as_double((long long)c->acc[ACC_ZINF]);
-  for (int k = 0; k < NACC; ++k) c->acc[k] = 0ull;
+  const double rp = m[ACC_RP], rin = m[ACC_RIN], rd = m[ACC_RD], zinf = m[ACC_ZINF];
   sc[SC_RP] = rp;
   sc[SC_RIN] = rin;
   sc[SC_RD] = rd;
@@ -48,9 +63,9 @@ __device__ __forceinline__ void finalize_body(const Net& n, const State& s, cons
   }
 }
 
-__global__ void k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void k_finalize_group(Group gr) {
+__global__ void __launch_bounds__(BLOCK) k_finalize_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
@@ -79,7 +94,7 @@ __global__ void __launch_bounds__(BLOCK) k_lambda_group(Group gr) {
 }
 
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, n, s, p);
 }
 
 int lambda_blocks(const Net& n) {
@@ -95,7 +110,7 @@ void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st) {
 }
 
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(64), 0, st, g);
+  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_lambda_group, dim3(grid), dim3(BLOCK), 0, st, g);

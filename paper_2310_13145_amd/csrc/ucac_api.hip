@@ -48,6 +48,8 @@ struct ucac_handle {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_poll = nullptr;
+  hipStream_t side = nullptr;                       // second capture stream of the iteration graph
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // capture-time fork/join of the graph
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
@@ -79,6 +81,9 @@ bool finite_all(const double* a, size_t n) {
     if (!std::isfinite(a[i])) return false;
   return true;
 }
+
+// Wavefronts of the line kernel at either block size (64 or 256): one counter slot each.
+size_t branch_waves_of(size_t TL) { return ((TL + 255) / 256) * 4; }
 
 size_t state_doubles(size_t N, size_t L, size_t G, size_t T) {
   return T * L * (10 + 4 + 3 * NRB) + T * G * (11 + 5 + 3 * NRG) + T * N * 2 + NSC;
@@ -160,6 +165,8 @@ struct Arena {
 
 // Carve every device array out of one allocation.  With base == nullptr only the
 // size is computed.
+size_t branch_waves(const ucac_handle* h) { return branch_waves_of((size_t)h->T * h->L); }
+
 size_t carve(ucac_handle* h, char* base) {
   const size_t N = h->N, L = h->L, G = h->G, T = h->T;
   Arena a{base, 0};
@@ -180,7 +187,13 @@ size_t carve(ucac_handle* h, char* base) {
   h->d_state = a.take<double>(h->n_state);
   s.ub_nxt = a.take<double>(3 * T * G);
   s.br_iters = a.take<int>(T * L);
-  s.br_count = a.take<unsigned long long>(5);
+  s.x0 = a.take<float>(4 * T * L);
+  s.br_count = a.take<unsigned long long>(branch_waves(h) * 5);
+  s.red_ubar = 0;
+  s.red_bus = s.red_ubar + ubar_blocks(n);
+  s.red_gdual = s.red_bus + bus_blocks(n);
+  s.red_n = s.red_gdual + gen_dual_blocks(n);
+  s.red = a.take<double>((size_t)s.red_n * NACC);
   s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
   s.log_cap = 0; s.log_stride = 1; s.log_phase = 0;
   h->d_ctl = a.take<Ctl>(1);
@@ -405,28 +418,49 @@ Par kernel_params(const ucac_params& p) {
   return k;
 }
 
-// Launch one inner iteration; returns the first launch error (with the kernel's name).
-hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
-  struct Step { const char* name; void (*fn)(const Net&, const State&, const Par&, hipStream_t); };
-  static const Step steps[] = {
-      {"uc_dp", launch_uc_dp},          // step:uc
-      {"gen", launch_gen},              // step:opf (generators)
-      {"branch", launch_branch},        // step:opf (lines)
-      {"ubar", launch_ubar},            // step:uc_bar  (reads the previous pbar)
-      {"bus", launch_bus},              // step:opf_bar (reads the previous ubar); line/G rows' z, y
-      {"gen_dual", launch_gen_dual},    // z, y of coupling and commitment rows
-      {"finalize", launch_finalize},    // residuals, inner/outer decision
-      {"lambda", launch_lambda},        // step:outer lambda update when decided
-  };
-  for (const Step& k : steps) {
-    k.fn(h->net, h->st, h->kp, st);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-      if (where) *where = k.name;
-      return e;
-    }
+// Enqueue one inner iteration for capture.  step:uc and the generator part of
+// step:opf do not depend on the line kernel, and step:uc_bar depends only on them
+// (it reads the previous pbar, which the bus kernel then overwrites), so these three
+// run on a side stream beside the line kernel; the bus kernel joins both paths:
+//
+//   main: branch ---------------------------+-> bus -> gen_dual -> finalize -> lambda
+//   side: uc_dp -> gen -> ubar -------------+
+//
+// launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError().
+template <class F>
+hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t fork, hipEvent_t join,
+                          const char** where) {
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
+  hipError_t e = hipEventRecord(fork, main);
+  if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+  if (e != hipSuccess) { if (where) *where = "fork"; return e; }
+  const int side_k[] = {K_UC_DP, K_GEN, K_UBAR};
+  for (int k : side_k) {
+    e = launch(k, side);
+    if (e != hipSuccess) { if (where) *where = names[k]; return e; }
+  }
+  e = hipEventRecord(join, side);
+  if (e != hipSuccess) { if (where) *where = "join"; return e; }
+  e = launch(K_BRANCH, main);
+  if (e != hipSuccess) { if (where) *where = names[K_BRANCH]; return e; }
+  e = hipStreamWaitEvent(main, join, 0);
+  if (e != hipSuccess) { if (where) *where = "join"; return e; }
+  const int main_k[] = {K_BUS, K_GEN_DUAL, K_FINALIZE, K_LAMBDA};
+  for (int k : main_k) {
+    e = launch(k, main);
+    if (e != hipSuccess) { if (where) *where = names[k]; return e; }
   }
   return hipSuccess;
+}
+
+hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
+  static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_gen_dual, launch_finalize, launch_lambda};
+  auto launch = [&](int k, hipStream_t s) {
+    fns[k](h->net, h->st, h->kp, s);
+    return hipGetLastError();
+  };
+  return enqueue_forked(launch, st, h->side, h->ev_fork, h->ev_join, where);
 }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
@@ -557,7 +591,11 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipHostMalloc((void**)&h->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_sc, sizeof(double) * NSC, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(h, UCAC_E_NOMEM, "pinned host allocation failed"));
-  if (hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
+  if (hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "stream create failed"));
 
   const Net& n = h->net;
   struct Up { void* dst; const void* src; size_t bytes; } ups[] = {
@@ -585,7 +623,8 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   }
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
-      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 5) != hipSuccess)
+      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 5 * branch_waves(h)) != hipSuccess ||
+      hipMemset(h->st.red, 0, sizeof(double) * NACC * h->st.red_n) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
   if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
@@ -796,8 +835,13 @@ int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset) {
   if (!h || !out) return h ? fail(h, UCAC_E_INVAL, "null output") : UCAC_E_INVAL;
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
-  HIP_OR(h, hipMemcpy(out, h->st.br_count, sizeof(uint64_t) * 5, hipMemcpyDeviceToHost));
-  if (reset) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 5));
+  const size_t nw = branch_waves(h);
+  std::vector<uint64_t> part(nw * 5);
+  if (nw) HIP_OR(h, hipMemcpy(part.data(), h->st.br_count, sizeof(uint64_t) * 5 * nw, hipMemcpyDeviceToHost));
+  for (int k = 0; k < 5; ++k) out[k] = 0;
+  for (size_t w = 0; w < nw; ++w)
+    for (int k = 0; k < 5; ++k) out[k] += part[w * 5 + k];
+  if (reset && nw) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 5 * nw));
   return UCAC_OK;
 }
 
@@ -1109,6 +1153,9 @@ void ucac_destroy(ucac_handle* h) {
   if (h->exec) (void)hipGraphExecDestroy(h->exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_sc) (void)hipHostFree(h->h_sc);
@@ -1125,7 +1172,8 @@ struct ucac_batch {
   int device = 0;
   int warm_start = 0;
   std::vector<ucac_handle*> m;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Member* d_members = nullptr;
   int* d_tables = nullptr;       // per kernel: blk_member [grid], blk_first [n], blk_count [n]
   Group grp[K_COUNT]{};
@@ -1208,25 +1256,23 @@ int batch_build(ucac_batch* b) {
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   (void)hipGetLastError();
   BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
-  hipError_t le = hipSuccess;
   const char* where = "";
-  for (int k = 0; k < K_COUNT && le == hipSuccess; ++k) {
-    if (b->grid[k] == 0) continue;
+  auto launch = [&](int k, hipStream_t s) {
+    if (b->grid[k] == 0) return hipSuccess;
     const Group& g = b->grp[k];
     switch (k) {
-      case K_UC_DP: launch_uc_dp_grouped(g, b->grid[k], b->cfg.dp_lanes, b->max_T, b->st); break;
-      case K_GEN: launch_gen_grouped(g, b->grid[k], b->st); break;
-      case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, b->st); break;
-      case K_UBAR: launch_ubar_grouped(g, b->grid[k], b->st); break;
-      case K_BUS: launch_bus_grouped(g, b->grid[k], b->st); break;
-      case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], b->st); break;
-      case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], b->st); break;
-      default: launch_lambda_grouped(g, b->grid[k], b->st); break;
+      case K_UC_DP: launch_uc_dp_grouped(g, b->grid[k], b->cfg.dp_lanes, b->max_T, s); break;
+      case K_GEN: launch_gen_grouped(g, b->grid[k], s); break;
+      case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, s); break;
+      case K_UBAR: launch_ubar_grouped(g, b->grid[k], s); break;
+      case K_BUS: launch_bus_grouped(g, b->grid[k], s); break;
+      case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], s); break;
+      case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], s); break;
+      default: launch_lambda_grouped(g, b->grid[k], s); break;
     }
-    le = hipGetLastError();
-    if (le != hipSuccess) where = names[k];
-  }
+    return hipGetLastError();
+  };
+  const hipError_t le = enqueue_forked(launch, b->st, b->side, b->ev_fork, b->ev_join, &where);
   const hipError_t ce = hipStreamEndCapture(b->st, &b->graph);
   if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
   if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
@@ -1287,8 +1333,11 @@ int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* pa
     b->max_T = std::max(b->max_T, h->T);
   }
   if (hipSetDevice(b->device) != hipSuccess) return bad(bfail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed"));
-  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess)
-    return bad(bfail(nullptr, UCAC_E_DEVICE, "stream create failed"));
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)
+    return bad(bfail(nullptr, UCAC_E_DEVICE, "stream/event create failed"));
   std::vector<Member> hm(n);
   for (int k = 0; k < n; ++k) hm[k] = Member{b->m[k]->net, b->m[k]->st, b->m[k]->kp};
   if (hipMalloc(&b->d_members, sizeof(Member) * n) != hipSuccess ||
@@ -1461,6 +1510,9 @@ void ucac_batch_destroy(ucac_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_members) (void)hipFree(b->d_members);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->st) (void)hipStreamDestroy(b->st);
   for (ucac_handle* h : b->m) ucac_destroy(h);
   delete b;

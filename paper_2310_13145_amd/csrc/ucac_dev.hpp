@@ -25,7 +25,6 @@ constexpr double TWO_PI = 6.283185307179586;
 // Device-resident control block of the iteration (never captured memsets: the
 // finalize kernel clears the accumulators after reading them).
 struct Ctl {
-  unsigned long long acc[NACC];  // max-reductions as the bit patterns of non-negative doubles
   int halt;                      // set once converged in solve mode: every kernel returns at entry
   int stop_at_tol;               // solve mode
   int pending;                   // this iteration ended an inner loop: lambda kernel applies step:outer
@@ -67,7 +66,11 @@ struct State {
   double* sc;                                                  // [NSC]
   double* ub_nxt;                                              // [3][T][G] new relaxed commitments
   int* br_iters;                                               // [T][L]
-  unsigned long long* br_count;  // [5] running totals: evaluations, trial evaluations, CG its, Newton its, learned-start fallbacks
+  unsigned long long* br_count;  // [waves][5] running totals per wavefront of the line kernel (global lane / 64):
+                                 // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks
+  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus and gen_dual
+  int red_ubar, red_bus, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
+  float* x0;                     // [4][T][L] start points of the learned Newton start (FP32)
   float* log_feat;               // null, or [log_cap][20] logged inputs of the learned start
   float* log_targ;               // [log_cap][4] logged solutions
   int* log_count;
@@ -126,12 +129,13 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Block-wide max of NV non-negative values, then one atomicMax per value.  The
-// IEEE bit patterns of non-negative doubles order like the values and a NaN
-// pattern exceeds every finite one, so the result is exact and independent of
-// the order in which blocks arrive.
+// Block-wide maxima of NV non-negative values, stored without atomics into this
+// block's slot of NACC doubles (slot[which[k]] = max of value k; the other entries
+// 0).  The finalize kernel reduces the slots of every block.  One slot per block
+// instead of device-scope atomics on a few shared addresses: those serialize at
+// the memory side of the chip, across its XCDs' separate L2 caches.
 template <int NV>
-__device__ inline void block_max_to_ctl(const double (&v)[NV], const int (&slot)[NV], Ctl* ctl) {
+__device__ inline void block_max_store(const double (&v)[NV], const int (&which)[NV], double* slot) {
   __shared__ double red[NV][BLOCK / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double w[NV];
@@ -143,12 +147,15 @@ __device__ inline void block_max_to_ctl(const double (&v)[NV], const int (&slot)
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    double out[NACC] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double m = red[k][0];
       for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = nmax(m, red[k][i]);
-      atomicMax(&ctl->acc[slot[k]], (unsigned long long)__double_as_longlong(m));
+      out[which[k]] = m;
     }
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) slot[k] = out[k];
   }
 }
 

@@ -39,31 +39,42 @@ __device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) { return __builtin_a
 
 __device__ inline int d_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
 
-// In place: X [64][K] (LDS rows, stride MLP_LD) becomes act(X W^T + b) [64][NOUT]
-// with W [NOUT][K] BF16 in global memory.  Each 32-row tile's products are all
-// formed before the tile is overwritten; the block barriers order the LDS reads
-// of every lane before the writes, so every lane of the block must call this.
+// SiLU from the hardware exponential and reciprocal (inference only; relative
+// error ~1e-6 before the result is rounded to BF16).
+__device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+// In place: X [64 samples][K] (LDS rows, stride MLP_LD) becomes
+// silu(X W^T + b) [64][NOUT], computed as the product W X^T so that the MFMA
+// result of a lane is four consecutive outputs of one sample (one 8-byte LDS
+// store): A = W rows (global), B = X rows (LDS), D[out][sample].  Each 32-sample
+// tile is read completely before it is overwritten; the block barriers order the
+// reads of every lane before the writes, so every lane of the block calls this.
 template <int K, int NOUT>
 __device__ inline void layer_silu_inplace(__bf16* X, const __bf16* W, const float* bias) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
-  for (int tm = 0; tm < 2; ++tm) {
+  for (int ts = 0; ts < 2; ++ts) {  // sample tile
     f32x16 acc[NOUT / 32];
 #pragma unroll
-    for (int tn = 0; tn < NOUT / 32; ++tn) {
-      acc[tn] = f32x16{};
+    for (int to = 0; to < NOUT / 32; ++to) {
+      acc[to] = f32x16{};
 #pragma unroll
       for (int ks = 0; ks < K / 16; ++ks)
-        acc[tn] = mfma(ld8(X + (tm * 32 + r) * MLP_LD + ks * 16 + h * 8), ld8(W + (tn * 32 + r) * K + ks * 16 + h * 8), acc[tn]);
+        acc[to] = mfma(ld8(W + (to * 32 + r) * K + ks * 16 + h * 8), ld8(X + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[to]);
     }
     __syncthreads();
+    __bf16* row = X + (ts * 32 + r) * MLP_LD;
 #pragma unroll
-    for (int tn = 0; tn < NOUT / 32; ++tn) {
-      const int n = tn * 32 + r;
-      const float bn = bias[n];
+    for (int to = 0; to < NOUT / 32; ++to)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) X[(tm * 32 + d_row(j, h)) * MLP_LD + n] = (__bf16)silu_f(acc[tn][j] + bn);
-    }
+      for (int jb = 0; jb < 4; ++jb) {
+        const int o = to * 32 + 8 * jb + 4 * h;  // outputs o .. o+3 of sample ts*32 + r
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (__bf16)silu_fast(acc[to][4 * jb + q] + bias[o + q]);
+        *reinterpret_cast<bf16x4*>(row + o) = v;
+      }
     __syncthreads();
   }
 }
@@ -73,26 +84,37 @@ __device__ inline void layer_silu_inplace(__bf16* X, const __bf16* W, const floa
 // block must call this (block barriers inside).  out: this lane's 4 outputs.
 __device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN], __bf16* buf, float (&out)[MLP_OUT]) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    __bf16* row = buf + lane * MLP_LD;
 #pragma unroll
-  for (int k = 0; k < MLP_KIN; ++k) buf[lane * MLP_LD + k] = (__bf16)(k < MLP_IN ? feat[k] : 0.0f);
+    for (int k = 0; k < MLP_KIN; k += 4) {
+      bf16x4 v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = (__bf16)(k + q < MLP_IN ? feat[k + q] : 0.0f);
+      *reinterpret_cast<bf16x4*>(row + k) = v;
+    }
+  }
   __syncthreads();
   layer_silu_inplace<MLP_KIN, MLP_H>(buf, w.W1b, w.b1);
   layer_silu_inplace<MLP_H, MLP_H>(buf, w.W2b, w.b2);
+  // output layer, W3 padded to 32 rows: outputs 0..3 of sample ts*32 + r sit in
+  // acc[0..3] of lane r (h = 0)
   f32x16 acc[2];
 #pragma unroll
-  for (int tm = 0; tm < 2; ++tm) {
-    acc[tm] = f32x16{};
+  for (int ts = 0; ts < 2; ++ts) {
+    acc[ts] = f32x16{};
 #pragma unroll
     for (int ks = 0; ks < MLP_H / 16; ++ks)
-      acc[tm] = mfma(ld8(buf + (tm * 32 + r) * MLP_LD + ks * 16 + h * 8), ld8(w.W3b + r * MLP_H + ks * 16 + h * 8), acc[tm]);
+      acc[ts] = mfma(ld8(w.W3b + r * MLP_H + ks * 16 + h * 8), ld8(buf + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[ts]);
   }
   __syncthreads();
   float* Yf = reinterpret_cast<float*>(buf);  // [64][4] FP32 over the consumed activations
-  if (r < MLP_OUT) {
+  if (h == 0) {
 #pragma unroll
-    for (int tm = 0; tm < 2; ++tm)
+    for (int ts = 0; ts < 2; ++ts)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) Yf[(tm * 32 + d_row(j, h)) * MLP_OUT + r] = acc[tm][j] + w.b3[r];
+      for (int o = 0; o < MLP_OUT; ++o) Yf[(ts * 32 + r) * MLP_OUT + o] = acc[ts][o] + w.b3[o];
   }
   __syncthreads();
 #pragma unroll
