@@ -43,7 +43,12 @@ BYTES_BRANCH = 8 * 36 + 4   # x-bar (8), z, y (16), nu (2) in; x (4), flows (4),
 BYTES_GEN = 8 * 29          # duplicates (5), z, y (16) in; p, q, six slacks out
 BYTES_UBAR = 8 * 40
 BYTES_GEN_DUAL = 8 * 66
-BYTES_BUS_PER_END = 8 * 28  # per incident line end; plus per unit 24 and per bus 6 doubles
+BYTES_BUS_PRE = 8 * 32 + 8  # per (line, t): both ends' flows, v, angle, z/y of 4 rows in; 8 sums out; positions
+BYTES_BUS_END = 8 * 4       # bus QP: the 4 sums of each incident line end
+BYTES_BUS_BUS = 8 * 8       # bus QP per (bus, t): wbar, thetabar in/out, 2 multipliers out, loads
+BYTES_BUS_GEN = 8 * 30      # bus QP per (unit, t): consensus and next-period ramp rows, duplicates out
+BYTES_BUS_POST = 8 * 64     # per (line, t), both ends: flows, targets, bus results, old duplicates, y/lambda of
+                            # 4 rows in; duplicates and z/y of 4 rows out
 
 
 # HBM bytes per dispatch of the plain-start line kernel, from two rocprofv3 --pmc runs
@@ -51,8 +56,8 @@ BYTES_BUS_PER_END = 8 * 28  # per incident line end; plus per unit 24 and per bu
 # mesh2000_T24 bench command), each scaled by the ratio of true to counted bytes of a
 # plain copy kernel of known size.  They describe the kernel source they were taken
 # on (hash below) and are reported as null once that source has changed.
-BRANCH_COUNTERS = {"source_sha256": "b3d66fca26186613981a494c0423ed453b74a8efc9276995ed5ac6d16c0243c2",
-                   "fetch_kib": 7881.39, "write_kib": 6450.00, "fetch_scale": 2.0, "write_scale": 1.0}
+BRANCH_COUNTERS = {"source_sha256": "6fc46a19749679614286025a7b9fa06ff6d88a2c1904d0ab1c7d954853ea85e7",
+                   "fetch_kib": 7885.71, "write_kib": 6346.88, "fetch_scale": 2.0, "write_scale": 1.0}
 BRANCH_SOURCES = ("k_branch.hip", "ucac_mlp.hpp")  # the line kernel's own code
 
 
@@ -91,6 +96,7 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=200)
     ap.add_argument("--learned-max-iters", type=int, default=4000)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--no-dp", action="store_true", help="skip the standalone DP benchmark")
     ap.add_argument("--batch-steps", type=int, default=100)
     return ap.parse_args()
 
@@ -107,8 +113,19 @@ def cpu_baseline(inst, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or n >= 200:
             break
-    return dict(value=n / el, unit="iters/s", cores=1, kind="oracle",
-                sample=f"first {n} inner iterations from the cold start of the same workload, {el:.1f} s, one thread")
+    res = dict(value=n / el, unit="iters/s", cores=1, kind="oracle",
+               sample=f"first {n} inner iterations from the cold start of the same workload, {el:.1f} s, one thread")
+    # the oracle's DP alone on the tables of the standalone DP benchmark (200 units per shape)
+    dp = {}
+    for G, T in DP_SHAPES:
+        tab, (tu, td, u0, lon, loff) = _dp_case(G, T, 7 + G + T)
+        k = min(G, 200)
+        t0 = time.perf_counter()
+        for g in range(k):
+            oracle.dp(tab[g], u0[g], lon[g], loff[g], tu[g], td[g])
+        dp[f"G{G}_T{T}"] = {"dp_per_s": k / (time.perf_counter() - t0), "sample": f"{k} units"}
+    res["dp"] = dp
+    return res
 
 
 def time_to_tol(ucac, torch, inst, args):
@@ -216,6 +233,43 @@ def learned_start(ucac, synth, torch, args):
     return out
 
 
+DP_SHAPES = [(g, t) for g in (1000, 10000) for t in (24, 48, 96, 168)]
+
+
+def _dp_case(G, T, seed):
+    rng = np.random.default_rng(seed)
+    tab = rng.normal(0.0, 1.0, size=(G, T, 2, 2))
+    ints = [rng.integers(1, 5, G), rng.integers(1, 5, G), rng.integers(0, 2, G), np.zeros(G), np.zeros(G)]
+    return tab, [x.astype(np.int32) for x in ints]
+
+
+def dp_standalone(ucac, torch, reps=20):
+    """The UC dynamic program alone at the shapes of the paper's DP experiment
+    (1,000 and 10,000 units, T = 24 ... 168; seeded random tables resident on the
+    GPU): DPs per second with the faster of 64 and 16 lanes per unit."""
+    out = {}
+    dev = torch.device("cuda:0")
+    for G, T in DP_SHAPES:
+        tab, ints = _dp_case(G, T, 7 + G + T)
+        args = [torch.from_numpy(tab).to(dev)] + [torch.from_numpy(x).to(dev) for x in ints]
+        best = None
+        for lanes in (64, 16):
+            try:
+                ucac.ucac_dp_batch(*args, lanes_per_unit=lanes)
+            except ucac.UcacError:
+                continue  # horizon too long for 4 units per block
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ucac.ucac_dp_batch(*args, lanes_per_unit=lanes)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / reps
+            if best is None or sec < best[0]:
+                best = (sec, lanes)
+        out[f"G{G}_T{T}"] = {"ms_per_batch": 1e3 * best[0], "dp_per_s": G / best[0], "lanes_per_unit": best[1]}
+    return out
+
+
 def batching(ucac, synth, torch, args):
     """64 independent instances of uneven size (30 to 2000 buses, T in {12, 24, 48}):
     one grouped launch per kernel with the tuned mapping, against running the same
@@ -290,9 +344,10 @@ def main():
                         cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
     br_s = ktimes["branch"] * 1e-3
     achieved = flops_per_launch / br_s / 1e12
-    n_ends = 2 * L
-    bytes_bus = n_ends * T * BYTES_BUS_PER_END + G * T * 8 * 24 + N * T * 8 * 6
+    bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
     hbm = {
+        "bus_pre": {"bytes": lanes * BYTES_BUS_PRE, "ms": ktimes["bus_pre"]},
+        "bus_post": {"bytes": lanes * BYTES_BUS_POST, "ms": ktimes["bus_post"]},
         "gen": {"bytes": G * T * BYTES_GEN, "ms": ktimes["gen"]},
         "ubar": {"bytes": G * T * BYTES_UBAR, "ms": ktimes["ubar"]},
         "bus": {"bytes": bytes_bus, "ms": ktimes["bus"]},
@@ -336,12 +391,18 @@ def main():
     if not args.no_batch:
         out["batching"] = batching(ucac, synth, torch, args)
 
+    if not args.no_dp:
+        out["dp_standalone"] = dp_standalone(ucac, torch)
+
     if not args.no_learned:
         out["learned_start"] = learned_start(ucac, synth, torch, args)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+        if "dp_standalone" in out:
+            for k, v in out["dp_standalone"].items():
+                v["gpu_over_cpu"] = v["dp_per_s"] / out["cpu_baseline"]["dp"][k]["dp_per_s"]
 
     solver.close()
     print(json.dumps(out), flush=True)

@@ -142,11 +142,14 @@ int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes);
 /* Newton iterations of the last line solve, per (t, line): [T][n_line]. */
 int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
 
-/* Number of kernels in one inner iteration, in launch order: UC dynamic program,
- * generators, lines (trust-region Newton), relaxed commitments, buses (with the
- * line and generator-consensus multipliers), coupling/commitment multipliers,
- * control (residuals and inner/outer decision), outer lambda update. */
-#define UCAC_N_KERNELS 8
+/* Number of kernels in one inner iteration, in the order ucac_kernel_times
+ * reports them: UC dynamic program, generators, lines (trust-region Newton; with
+ * the learned start this slot also times the network), relaxed commitments, bus
+ * QP in three passes (line-end sums, bus solve with the generator-consensus
+ * multipliers, line-end duplicates with the line multipliers),
+ * coupling/commitment multipliers, control (residuals and inner/outer decision),
+ * outer lambda update. */
+#define UCAC_N_KERNELS 10
 
 /* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
  * with every kernel launched on its own and a HIP event recorded on the handle's
@@ -166,6 +169,24 @@ int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
  * iteration of that call at which both r_primal and r_dual were <= 1e-2, 1e-3,
  * 1e-4 respectively, or -1 if never.  Recorded on the device every iteration. */
 int ucac_solve_milestones(const ucac_handle* h, int32_t* first_iter);
+
+/* ---- the UC dynamic program on its own (Sec. III-B, Alg. dp_algo) -----------
+ * G independent unit-commitment DPs over T periods, one per unit, on tables the
+ * caller supplies: tab[g][t][s'][s] (FP64, row-major) is the cost of period t
+ * when the unit was in state s' before and is in state s (0 off, 1 on) in t.
+ * min_up, min_dn (T^U, T^D; values below 1 act as 1), u0 (initial state 0/1),
+ * hold_on, hold_off (L_g, F_g: periods the initial state must still be held)
+ * are int32 [G].  Outputs: u_on[g][t] (int8 0/1) and cost[g], the optimal total
+ * (the stay/switch recursion with "stay" on ties).  Every pointer is DEVICE
+ * memory owned by the caller; the call only enqueues the work on `stream` (a
+ * hipStream_t, or NULL for the default stream) and returns: synchronize before
+ * reading the outputs.  lanes_per_unit: 64 (one wavefront per unit) or 16 (four
+ * units per wavefront).  UCAC_E_INVAL if the horizon's LDS exceeds 64 KiB per
+ * block (T above about 1200 with 64 lanes, about 300 with 16).  Errors are read
+ * with ucac_last_error(NULL). */
+int ucac_dp_batch(int32_t G, int32_t T, const double* tab, const int32_t* min_up, const int32_t* min_dn,
+                  const int32_t* u0, const int32_t* hold_on, const int32_t* hold_off, int8_t* u_on, double* cost,
+                  int32_t lanes_per_unit, void* stream);
 
 /* ---- learned warm start of the line Newton solves --------------------------
  * A 20 -> 64 -> 64 -> 4 perceptron with SiLU activations, BF16 weights and FP32

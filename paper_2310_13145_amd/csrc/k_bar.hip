@@ -5,11 +5,18 @@
 //            C6(t+1), U2(t+1)); the first period also solves ubar_su_1.  Writes
 //            the new values to a side buffer so that the bus kernel still reads
 //            the previous ones (the Jacobi pair uc_bar || opf_bar).
-// k_bus      one lane per (bus, t): the diagonal QP of every bus-side duplicate
-//            subject to the P and Q balance equations, solved through its 2x2
-//            KKT system; thetabar is a weighted mean (zero at the reference bus).
-//            The lane then updates z and y of every row it owns: the four rows of
-//            each incident line end and G1, G2 of its generators.
+// step:opf_bar -- the diagonal QP of every bus-side duplicate subject to the P and Q
+//            balance equations (2x2 KKT system per bus; thetabar a weighted mean,
+//            zero at the reference bus) -- in three coalesced passes:
+// k_bus_pre  one lane per (line, t): per line end, the four quantities the bus sums
+//            need (P and Q targets, v^2 and angle centres), stored in the bus
+//            incidence (CSR) order so that each bus reads one contiguous range;
+// k_bus      one lane per (bus, t): sums its ends' quantities in incidence order,
+//            solves the KKT system, writes wbar, thetabar and the two balance
+//            multipliers, and updates its generators' duplicates and rows G1, G2;
+// k_bus_post one lane per (line, t): Pbar, Qbar of both ends from the end buses'
+//            multipliers, and z, y of the line's eight rows.
+// The arithmetic is the one-pass gather's, in the same order.
 // k_gen_dual one lane per (g, t): z and y of rows C1..C6 and U1..U3, and commits
 //            the new relaxed commitments.
 // Each kernel stores its blocks' residual maxima into per-block slots.
@@ -125,11 +132,7 @@ __device__ inline void zy_update(double* zr, double* yr, const double* lr, int k
   zinf = nmax(zinf, fabs(z));
 }
 
-// Line ends of a bus are visited in groups of GROUP with predicated (clamped)
-// loads, so each group's gathers are issued together as straight-line code: the
-// kernel is bound by gather latency, and this gives every lane GROUP loads in
-// flight instead of one dependent chain per line end.
-constexpr int GROUP = 4;
+
 
 struct EndData {
   int k, rP, rQ, rW, rT;
@@ -150,10 +153,31 @@ __device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, 
   return d;
 }
 
+__device__ __forceinline__ void bus_pre_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+  if (s.ctl->halt) return;
+  const int TL = n.T * n.L;
+  const int idx = blk * BLOCK + threadIdx.x;
+  if (idx >= TL) return;
+  const int t = idx / n.L, l = idx - t * n.L;
+  const double rpq = p.rho_pq, rva = p.rho_va;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int code = 2 * l + side;
+    const EndData d = load_end(n, s, t, TL, code, rpq);
+    const double zW = s.zB[d.rW * TL + d.k], yW = s.yB[d.rW * TL + d.k];
+    const double zT = s.zB[d.rT * TL + d.k], yT = s.yB[d.rT * TL + d.k];
+    double* o = s.ebuf + ((size_t)t * 2 * n.L + n.end_pos[code]) * 4;
+    o[0] = d.tP;
+    o[1] = d.tQ;
+    o[2] = d.v * d.v + zW + yW / rva;
+    o[3] = d.th + zT + yT / rva;
+  }
+}
+
 __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
-  const int TL = T * n.L, TG = T * G;
+  const int TG = T * G;
   const int idx = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
@@ -163,33 +187,17 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
-    for (int e = e0; e < e1; e += GROUP) {
-      int code[GROUP];
-      double on[GROUP];
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) {
-        const bool in = e + j < e1;
-        code[j] = n.inc_code[in ? e + j : e0];
-        on[j] = in ? 1.0 : 0.0;
-      }
-      EndData d[GROUP];
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) d[j] = load_end(n, s, t, TL, code[j], rpq);
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) {
-        const double zW = s.zB[d[j].rW * TL + d[j].k], yW = s.yB[d[j].rW * TL + d[j].k];
-        const double zT = s.zB[d[j].rT * TL + d[j].k], yT = s.yB[d[j].rT * TL + d[j].k];
-        if (on[j] != 0.0) {
-          M11 += 1.0 / rpq;
-          aT -= d[j].tP;
-          M22 += 1.0 / rpq;
-          bT -= d[j].tQ;
-          Ww += rva;
-          Sw += rva * (d[j].v * d[j].v + zW + yW / rva);
-          Wt += rva;
-          St += rva * (d[j].th + zT + yT / rva);
-        }
-      }
+    const double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;
+    for (int e = e0; e < e1; ++e) {
+      const double* q = eb + (size_t)e * 4;
+      M11 += 1.0 / rpq;
+      aT -= q[0];
+      M22 += 1.0 / rpq;
+      bT -= q[1];
+      Ww += rva;
+      Sw += rva * q[2];
+      Wt += rva;
+      St += rva * q[3];
     }
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
     for (int e = g0; e < g1; ++e) {
@@ -225,41 +233,9 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double thnew = (i == n.ref) ? 0.0 : (Wt > 0.0 ? St / Wt : thold);
     s.wb[idx] = wnew;
     s.thb[idx] = thnew;
+    s.bmu[idx] = mu1;
+    s.bmu[T * N + idx] = mu2;
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
-    for (int e = e0; e < e1; e += GROUP) {
-      int code[GROUP];
-      bool on[GROUP];
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) {
-        on[j] = e + j < e1;
-        code[j] = n.inc_code[on[j] ? e + j : e0];
-      }
-      EndData d[GROUP];
-      double Pold[GROUP], Qold[GROUP];
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) {
-        d[j] = load_end(n, s, t, TL, code[j], rpq);
-        const bool side = code[j] & 1;
-        Pold[j] = side ? s.Pbt[d[j].k] : s.Pbf[d[j].k];
-        Qold[j] = side ? s.Qbt[d[j].k] : s.Qbf[d[j].k];
-      }
-#pragma unroll
-      for (int j = 0; j < GROUP; ++j) {
-        if (!on[j]) continue;
-        const bool side = code[j] & 1;
-        const int k = d[j].k;
-        const double Pn = d[j].tP - mu1 / rpq, Qn = d[j].tQ - mu2 / rpq;
-        double* Pdup = side ? s.Pbt : s.Pbf;
-        double* Qdup = side ? s.Qbt : s.Qbf;
-        rd = nmax(rd, nmax(fabs(Pn - Pold[j]), fabs(Qn - Qold[j])));
-        Pdup[k] = Pn;
-        Qdup[k] = Qn;
-        zy_update(s.zB + d[j].rP * TL, s.yB + d[j].rP * TL, s.lB + d[j].rP * TL, k, d[j].fP - Pn, rpq, beta, rp, rin, zinf);
-        zy_update(s.zB + d[j].rQ * TL, s.yB + d[j].rQ * TL, s.lB + d[j].rQ * TL, k, d[j].fQ - Qn, rpq, beta, rp, rin, zinf);
-        zy_update(s.zB + d[j].rW * TL, s.yB + d[j].rW * TL, s.lB + d[j].rW * TL, k, d[j].v * d[j].v - wnew, rva, beta, rp, rin, zinf);
-        zy_update(s.zB + d[j].rT * TL, s.yB + d[j].rT * TL, s.lB + d[j].rT * TL, k, d[j].th - thnew, rva, beta, rp, rin, zinf);
-      }
-    }
     for (int e = g0; e < g1; ++e) {
       const int g = n.gen_list[e], k = t * G + g;
       double Wp = rpq, Sp = rpq * (s.p[k] + s.zG[RG_G1 * TG + k] + s.yG[RG_G1 * TG + k] / rpq);
@@ -284,6 +260,57 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bus + blk) * NACC);
+}
+
+__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+  if (s.ctl->halt) return;
+  const int TL = n.T * n.L, TN = n.T * n.N;
+  const int idx = blk * BLOCK + threadIdx.x;
+  double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
+  if (idx < TL) {
+    const int t = idx / n.L, l = idx - t * n.L;
+    const double rpq = p.rho_pq, rva = p.rho_va;
+    const double beta = s.sc[SC_BETA];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int code = 2 * l + side;
+      const EndData d = load_end(n, s, t, TL, code, rpq);
+      const int b = t * n.N + (side ? n.to[l] : n.from[l]);
+      const double mu1 = s.bmu[b], mu2 = s.bmu[TN + b], wnew = s.wb[b], thnew = s.thb[b];
+      double* Pdup = side ? s.Pbt : s.Pbf;
+      double* Qdup = side ? s.Qbt : s.Qbf;
+      const int k = d.k;
+      const double Pn = d.tP - mu1 / rpq, Qn = d.tQ - mu2 / rpq;
+      rd = nmax(rd, nmax(fabs(Pn - Pdup[k]), fabs(Qn - Qdup[k])));
+      Pdup[k] = Pn;
+      Qdup[k] = Qn;
+      zy_update(s.zB + d.rP * TL, s.yB + d.rP * TL, s.lB + d.rP * TL, k, d.fP - Pn, rpq, beta, rp, rin, zinf);
+      zy_update(s.zB + d.rQ * TL, s.yB + d.rQ * TL, s.lB + d.rQ * TL, k, d.fQ - Qn, rpq, beta, rp, rin, zinf);
+      zy_update(s.zB + d.rW * TL, s.yB + d.rW * TL, s.lB + d.rW * TL, k, d.v * d.v - wnew, rva, beta, rp, rin, zinf);
+      zy_update(s.zB + d.rT * TL, s.yB + d.rT * TL, s.lB + d.rT * TL, k, d.th - thnew, rva, beta, rp, rin, zinf);
+    }
+  }
+  const double v[4] = {rp, rin, rd, zinf};
+  const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
+  block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_bus_pre(Net n, State s, Par p) { bus_pre_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_bus_pre_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  bus_pre_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_bus_post(Net n, State s, Par p) { bus_post_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_bus_post_group(Group gr) {
+  const int mk = gr.blk_member[blockIdx.x];
+  const Member& M = gr.m[mk];
+  const int b0 = gr.blk_first[mk];
+  bus_post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
@@ -346,6 +373,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen_dual_group(Group gr) {
 
 int ubar_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
 int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
+int line_blocks(const Net& n) { return (n.T * n.L + BLOCK - 1) / BLOCK; }
 int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
 
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
@@ -353,6 +381,12 @@ void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
 }
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
+}
+void launch_bus_pre_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_bus_pre_group, dim3(grid), dim3(BLOCK), 0, st, g);
+}
+void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_bus_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(BLOCK), 0, st, g);
@@ -368,6 +402,18 @@ void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;
   if (TN == 0) return;
   hipLaunchKernelGGL(k_bus, dim3((TN + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+}
+
+void launch_bus_pre(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const int TL = n.T * n.L;
+  if (TL == 0) return;
+  hipLaunchKernelGGL(k_bus_pre, dim3(line_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
+}
+
+void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const int TL = n.T * n.L;
+  if (TL == 0) return;
+  hipLaunchKernelGGL(k_bus_post, dim3(line_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
 void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st) {

@@ -10,6 +10,10 @@
 
 namespace ucac {
 
+// One block of finalize per instance reduces every per-block residual slot of the
+// iteration (hundreds to a few thousand): many threads keep many loads in flight.
+constexpr int FIN_BLOCK = 256;
+
 __device__ __forceinline__ void finalize_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   Ctl* c = s.ctl;
   if (c->halt) return;
@@ -19,7 +23,7 @@ __device__ __forceinline__ void finalize_body(const Net& n, const State& s, cons
 #pragma unroll
     for (int k = 0; k < NACC; ++k) m[k] = nmax(m[k], s.red[(size_t)b * NACC + k]);
   }
-  __shared__ double part[NACC][BLOCK / 64];
+  __shared__ double part[NACC][FIN_BLOCK / 64];
 #pragma unroll
   for (int k = 0; k < NACC; ++k) m[k] = wave_max(m[k]);
   if ((threadIdx.x & 63) == 0) {
@@ -63,9 +67,9 @@ __device__ __forceinline__ void finalize_body(const Net& n, const State& s, cons
   }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(BLOCK) k_finalize_group(Group gr) {
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
@@ -94,7 +98,7 @@ __global__ void __launch_bounds__(BLOCK) k_lambda_group(Group gr) {
 }
 
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, n, s, p);
 }
 
 int lambda_blocks(const Net& n) {
@@ -110,7 +114,7 @@ void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st) {
 }
 
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(FIN_BLOCK), 0, st, g);
 }
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_lambda_group, dim3(grid), dim3(BLOCK), 0, st, g);

@@ -39,6 +39,58 @@ __host__ __device__ inline size_t dp_slot_bytes(int T) {
   return (b + 7) & ~(size_t)7;
 }
 
+// The stay/switch backward induction over the LDS table Lt (1-based period t at
+// Lt[(t-1)*4 + s'*2 + s]), the initial hold (L_g periods on or F_g off), and the
+// forward reconstruction of the schedule u[0..T).  Returns the optimal cost,
+// summed in the order of the recursion.  Minimum up/down times below 1 act as 1.
+__device__ inline double dp_recursion(int T, const double* Lt, double* c, unsigned char* dec, signed char* u, int u0,
+                                      int lon, int loff, int tu, int td) {
+  const int TU = tu < 1 ? 1 : tu, TD = td < 1 ? 1 : td;
+  int hold = u0 ? lon : loff;
+  hold = hold > T ? T : (hold < 0 ? 0 : hold);
+  c[(T + 1) * 2 + 0] = 0.0;
+  c[(T + 1) * 2 + 1] = 0.0;
+  for (int t = T; t >= 1 && t > hold; --t) {
+    for (int ss = 0; ss < 2; ++ss) {
+      const double stay = Lt[((t - 1) * 2 + ss) * 2 + ss] + c[(t + 1) * 2 + ss];
+      const int ns = 1 - ss;
+      const int Tm = ns ? TU : TD;
+      double sw = Lt[((t - 1) * 2 + ss) * 2 + ns];
+      const int last = (t + Tm - 1) < T ? (t + Tm - 1) : T;
+      for (int tp = t + 1; tp <= last; ++tp) sw += Lt[((tp - 1) * 2 + ns) * 2 + ns];
+      const int nxt = t + Tm;
+      sw += (nxt <= T) ? c[nxt * 2 + ns] : 0.0;
+      const bool keep = stay <= sw;
+      c[t * 2 + ss] = keep ? stay : sw;
+      dec[t * 2 + ss] = keep ? 0 : 1;
+    }
+  }
+  double cost;
+  int st = u0;
+  if (hold > 0) {
+    cost = 0.0;
+    for (int k = 1; k <= hold; ++k) cost += Lt[((k - 1) * 2 + u0) * 2 + u0];
+    cost += c[(hold + 1) * 2 + u0];
+  } else {
+    cost = c[1 * 2 + u0];
+  }
+  for (int k = 1; k <= hold; ++k) u[k - 1] = (signed char)u0;
+  int t = hold + 1;
+  while (t <= T) {
+    if (dec[t * 2 + st] == 0) {
+      u[t - 1] = (signed char)st;
+      ++t;
+    } else {
+      const int ns = 1 - st;
+      const int Tm = ns ? TU : TD;
+      for (int k = t; k <= t + Tm - 1 && k <= T; ++k) u[k - 1] = (signed char)ns;
+      t += Tm;
+      st = ns;
+    }
+  }
+  return cost;
+}
+
 // LPG lanes per generator (64: one wavefront; 16: four generators per wavefront).
 // The LPG lanes of a generator build its table; the group's first lane runs the
 // recursion and the reconstruction.  slotT: horizon the LDS slots are sized for.
@@ -74,44 +126,7 @@ __device__ __forceinline__ void uc_dp_body(const Net& n, const State& s, const P
   }
   __syncthreads();
 
-  if (act && lane == 0) {
-    const int u0 = n.u0[g], TU = n.tu[g], TD = n.td[g];
-    int hold = u0 ? n.lon[g] : n.loff[g];
-    hold = hold > T ? T : (hold < 0 ? 0 : hold);
-    // 1-based periods: entry of period t at Lt[(t-1)*4 + sp*2 + s]
-    c[(T + 1) * 2 + 0] = 0.0;
-    c[(T + 1) * 2 + 1] = 0.0;
-    for (int t = T; t >= 1 && t > hold; --t) {
-      for (int ss = 0; ss < 2; ++ss) {
-        const double stay = Lt[((t - 1) * 2 + ss) * 2 + ss] + c[(t + 1) * 2 + ss];
-        const int ns = 1 - ss;
-        const int Tm = ns ? TU : TD;
-        double sw = Lt[((t - 1) * 2 + ss) * 2 + ns];
-        const int last = (t + Tm - 1) < T ? (t + Tm - 1) : T;
-        for (int tp = t + 1; tp <= last; ++tp) sw += Lt[((tp - 1) * 2 + ns) * 2 + ns];
-        const int nxt = t + Tm;
-        sw += (nxt <= T) ? c[nxt * 2 + ns] : 0.0;
-        const bool keep = stay <= sw;
-        c[t * 2 + ss] = keep ? stay : sw;
-        dec[t * 2 + ss] = keep ? 0 : 1;
-      }
-    }
-    int t = 1, st = u0;
-    for (int k = 1; k <= hold; ++k) u[k - 1] = (signed char)u0;
-    t = hold + 1;
-    while (t <= T) {
-      if (dec[t * 2 + st] == 0) {
-        u[t - 1] = (signed char)st;
-        ++t;
-      } else {
-        const int ns = 1 - st;
-        const int Tm = ns ? TU : TD;
-        for (int k = t; k <= t + Tm - 1 && k <= T; ++k) u[k - 1] = (signed char)ns;
-        t += Tm;
-        st = ns;
-      }
-    }
-  }
+  if (act && lane == 0) dp_recursion(T, Lt, c, dec, u, n.u0[g], n.lon[g], n.loff[g], n.tu[g], n.td[g]);
   __syncthreads();
 
   if (act) {
@@ -137,6 +152,44 @@ __global__ void __launch_bounds__(64) k_uc_dp_group(Group gr, int slotT) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   uc_dp_body<LPG>(M.n, M.s, M.p, blockIdx.x - gr.blk_first[mk], slotT);
+}
+
+// Standalone batch of dynamic programs on given tables tab [G][T][2][2]: the same
+// recursion, with the table loaded instead of built from the ADMM rows.
+template <int LPG>
+__global__ void __launch_bounds__(64) k_dp_tables(const double* __restrict__ tab, int G, int T, const int* tu,
+                                                  const int* td, const int* u0, const int* lon, const int* loff,
+                                                  signed char* u_out, double* cost_out) {
+  constexpr int GPB = 64 / LPG;
+  const int sub = threadIdx.x / LPG, lane = threadIdx.x - sub * LPG;
+  const int g = blockIdx.x * GPB + sub;
+  const bool act = g < G;
+  extern __shared__ double lds[];
+  char* base = (char*)lds + dp_slot_bytes(T) * sub;
+  double* Lt = (double*)base;
+  double* c = Lt + 4 * T;
+  unsigned char* dec = (unsigned char*)(c + 2 * (T + 2));
+  signed char* u = (signed char*)(dec + 2 * (T + 2));
+  if (act) {
+    const double* src = tab + (size_t)g * T * 4;
+    for (int k = lane; k < 4 * T; k += LPG) Lt[k] = src[k];
+  }
+  __syncthreads();
+  if (act && lane == 0) cost_out[g] = dp_recursion(T, Lt, c, dec, u, u0[g], lon[g], loff[g], tu[g], td[g]);
+  __syncthreads();
+  if (act)
+    for (int t = lane; t < T; t += LPG) u_out[(size_t)g * T + t] = u[t];
+}
+
+size_t dp_tables_lds(int T, int lanes) { return dp_slot_bytes(T) * (64 / lanes); }
+
+void launch_dp_tables(const double* tab, int G, int T, const int* tu, const int* td, const int* u0, const int* lon,
+                      const int* loff, signed char* u_out, double* cost_out, int lanes, hipStream_t st) {
+  const int gpb = 64 / lanes;
+  const dim3 grid((G + gpb - 1) / gpb);
+  const size_t lds = dp_tables_lds(T, lanes);
+  if (lanes == 16) hipLaunchKernelGGL(k_dp_tables<16>, grid, dim3(64), lds, st, tab, G, T, tu, td, u0, lon, loff, u_out, cost_out);
+  else hipLaunchKernelGGL(k_dp_tables<64>, grid, dim3(64), lds, st, tab, G, T, tu, td, u0, lon, loff, u_out, cost_out);
 }
 
 int uc_dp_blocks(const Net& n, int dp_lanes) {

@@ -48,8 +48,8 @@ struct ucac_handle {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_poll = nullptr;
-  hipStream_t side = nullptr;                       // second capture stream of the iteration graph
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // capture-time fork/join of the graph
+  hipStream_t side = nullptr;        // second capture stream of the iteration graph
+  hipEvent_t ev[4] = {};             // capture-time fork/join events of the graph
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
@@ -177,7 +177,7 @@ size_t carve(ucac_handle* h, char* base) {
   n.adm = a.take<double>(8 * L); n.rate = a.take<double>(L);
   n.gs = a.take<double>(N); n.bs = a.take<double>(N); n.vmin = a.take<double>(N); n.vmax = a.take<double>(N);
   n.Pd = a.take<double>(T * N); n.Qd = a.take<double>(T * N);
-  n.inc_start = a.take<int>(N + 1); n.inc_code = a.take<int>(2 * L);
+  n.inc_start = a.take<int>(N + 1); n.inc_code = a.take<int>(2 * L); n.end_pos = a.take<int>(2 * L);
   n.gen_start = a.take<int>(N + 1); n.gen_list = a.take<int>(G);
   n.pmin = a.take<double>(G); n.pmax = a.take<double>(G); n.qmin = a.take<double>(G); n.qmax = a.take<double>(G);
   n.k2 = a.take<double>(G); n.k1 = a.take<double>(G); n.cnl = a.take<double>(G); n.csu = a.take<double>(G);
@@ -191,9 +191,12 @@ size_t carve(ucac_handle* h, char* base) {
   s.br_count = a.take<unsigned long long>(branch_waves(h) * 5);
   s.red_ubar = 0;
   s.red_bus = s.red_ubar + ubar_blocks(n);
-  s.red_gdual = s.red_bus + bus_blocks(n);
+  s.red_bpost = s.red_bus + bus_blocks(n);
+  s.red_gdual = s.red_bpost + line_blocks(n);
   s.red_n = s.red_gdual + gen_dual_blocks(n);
   s.red = a.take<double>((size_t)s.red_n * NACC);
+  s.ebuf = a.take<double>(T * 2 * L * 4);
+  s.bmu = a.take<double>(2 * T * N);
   s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
   s.log_cap = 0; s.log_stride = 1; s.log_phase = 0;
   h->d_ctl = a.take<Ctl>(1);
@@ -421,53 +424,64 @@ Par kernel_params(const ucac_params& p) {
 // Enqueue one inner iteration for capture.  step:uc and the generator part of
 // step:opf do not depend on the line kernel, and step:uc_bar depends only on them
 // (it reads the previous pbar, which the bus kernel then overwrites), so these three
-// run on a side stream beside the line kernel; the bus kernel joins both paths:
+// run on a side stream beside the line kernel.  After the bus QP, the line-side
+// finish (bus_post) and the coupling/commitment multipliers (gen_dual) touch
+// disjoint rows and run side by side again:
 //
-//   main: branch ---------------------------+-> bus -> gen_dual -> finalize -> lambda
-//   side: uc_dp -> gen -> ubar -------------+
+//   main: branch -> bus_pre --+-> bus --+-> bus_post ----+-> finalize -> lambda
+//   side: uc_dp -> gen -> ubar +        +-> gen_dual ----+
 //
-// launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError().
+// launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError();
+// ev[0..3]: capture-time fork/join events.
 template <class F>
-hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t fork, hipEvent_t join,
-                          const char** where) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
-  hipError_t e = hipEventRecord(fork, main);
-  if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
-  if (e != hipSuccess) { if (where) *where = "fork"; return e; }
-  const int side_k[] = {K_UC_DP, K_GEN, K_UBAR};
-  for (int k : side_k) {
-    e = launch(k, side);
-    if (e != hipSuccess) { if (where) *where = names[k]; return e; }
-  }
-  e = hipEventRecord(join, side);
-  if (e != hipSuccess) { if (where) *where = "join"; return e; }
-  e = launch(K_BRANCH, main);
-  if (e != hipSuccess) { if (where) *where = names[K_BRANCH]; return e; }
-  e = hipStreamWaitEvent(main, join, 0);
-  if (e != hipSuccess) { if (where) *where = "join"; return e; }
-  const int main_k[] = {K_BUS, K_GEN_DUAL, K_FINALIZE, K_LAMBDA};
-  for (int k : main_k) {
-    e = launch(k, main);
-    if (e != hipSuccess) { if (where) *where = names[k]; return e; }
-  }
-  return hipSuccess;
+hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t* ev, const char** where) {
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda"};
+  hipError_t e = hipSuccess;
+  auto run = [&](int k, hipStream_t s) {
+    if (e == hipSuccess) {
+      e = launch(k, s);
+      if (e != hipSuccess && where) *where = names[k];
+    }
+  };
+  auto link = [&](hipStream_t from, hipStream_t to, hipEvent_t evt) {
+    if (e == hipSuccess) e = hipEventRecord(evt, from);
+    if (e == hipSuccess) e = hipStreamWaitEvent(to, evt, 0);
+    if (e != hipSuccess && where && !*where) *where = "fork/join";
+  };
+  link(main, side, ev[0]);
+  run(K_UC_DP, side);
+  run(K_GEN, side);
+  run(K_UBAR, side);
+  run(K_BRANCH, main);
+  run(K_BUS_PRE, main);
+  link(side, main, ev[1]);
+  run(K_BUS, main);
+  link(main, side, ev[2]);
+  run(K_GEN_DUAL, side);
+  run(K_BUS_POST, main);
+  link(side, main, ev[3]);
+  run(K_FINALIZE, main);
+  run(K_LAMBDA, main);
+  return e;
 }
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_gen_dual, launch_finalize, launch_lambda};
+      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,     launch_bus_pre,
+      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize, launch_lambda};
   auto launch = [&](int k, hipStream_t s) {
     fns[k](h->net, h->st, h->kp, s);
     return hipGetLastError();
   };
-  return enqueue_forked(launch, st, h->side, h->ev_fork, h->ev_join, where);
+  return enqueue_forked(launch, st, h->side, h->ev, where);
 }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_gen_dual, launch_finalize, launch_lambda};
+      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,     launch_bus_pre,
+      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize, launch_lambda};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -558,6 +572,8 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
       inc_code[inc_start[to[l]] + fill[to[l]]++] = (int)(2 * l + 1);
     }
   }
+  std::vector<int> end_pos(2 * L);
+  for (size_t e = 0; e < 2 * L; ++e) end_pos[inc_code[e]] = (int)e;
   for (size_t g = 0; g < G; ++g) gen_start[net->gen_bus[g] + 1]++;
   for (size_t i = 0; i < N; ++i) gen_start[i + 1] += gen_start[i];
   {
@@ -591,10 +607,9 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipHostMalloc((void**)&h->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_sc, sizeof(double) * NSC, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(h, UCAC_E_NOMEM, "pinned host allocation failed"));
-  if (hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-    return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
+  bool ev_ok = hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) == hipSuccess;
+  for (hipEvent_t& e : h->ev) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ev_ok) return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "stream create failed"));
 
   const Net& n = h->net;
@@ -605,6 +620,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
       {(void*)n.vmin, net->bus_vmin, sizeof(double) * N}, {(void*)n.vmax, net->bus_vmax, sizeof(double) * N},
       {(void*)n.Pd, net->load_p, sizeof(double) * T * N}, {(void*)n.Qd, net->load_q, sizeof(double) * T * N},
       {(void*)n.inc_start, inc_start.data(), sizeof(int) * (N + 1)}, {(void*)n.inc_code, inc_code.data(), sizeof(int) * 2 * L},
+      {(void*)n.end_pos, end_pos.data(), sizeof(int) * 2 * L},
       {(void*)n.gen_start, gen_start.data(), sizeof(int) * (N + 1)}, {(void*)n.gen_list, gen_list.data(), sizeof(int) * G},
       {(void*)n.pmin, net->gen_pmin, sizeof(double) * G}, {(void*)n.pmax, net->gen_pmax, sizeof(double) * G},
       {(void*)n.qmin, net->gen_qmin, sizeof(double) * G}, {(void*)n.qmax, net->gen_qmax, sizeof(double) * G},
@@ -1144,6 +1160,25 @@ void ucac_mlp_destroy(ucac_mlp* m) {
   delete m;
 }
 
+int ucac_dp_batch(int32_t G, int32_t T, const double* tab, const int32_t* min_up, const int32_t* min_dn,
+                  const int32_t* u0, const int32_t* hold_on, const int32_t* hold_off, int8_t* u_on, double* cost,
+                  int32_t lanes_per_unit, void* stream) {
+  if (G < 0 || T < 1 || (lanes_per_unit != 16 && lanes_per_unit != 64))
+    return fail(nullptr, UCAC_E_INVAL, "dp_batch: need G >= 0, T >= 1, lanes_per_unit 16 or 64");
+  if (G == 0) return UCAC_OK;
+  if (!tab || !min_up || !min_dn || !u0 || !hold_on || !hold_off || !u_on || !cost)
+    return fail(nullptr, UCAC_E_INVAL, "dp_batch: null pointer");
+  if (dp_tables_lds(T, lanes_per_unit) > 65536)
+    return fail(nullptr, UCAC_E_INVAL, "dp_batch: horizon %d needs %zu bytes of LDS per block (limit 65536)", T,
+                dp_tables_lds(T, lanes_per_unit));
+  (void)hipGetLastError();
+  launch_dp_tables(tab, G, T, min_up, min_dn, u0, hold_on, hold_off, (signed char*)u_on, cost, lanes_per_unit,
+                   (hipStream_t)stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, UCAC_E_DEVICE, "dp_batch launch failed: %s", hipGetErrorString(e));
+  return UCAC_OK;
+}
+
 const char* ucac_last_error(const ucac_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
 void ucac_destroy(ucac_handle* h) {
@@ -1153,8 +1188,8 @@ void ucac_destroy(ucac_handle* h) {
   if (h->exec) (void)hipGraphExecDestroy(h->exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  for (hipEvent_t e : h->ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -1173,7 +1208,7 @@ struct ucac_batch {
   int warm_start = 0;
   std::vector<ucac_handle*> m;
   hipStream_t st = nullptr, side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev[4] = {};
   Member* d_members = nullptr;
   int* d_tables = nullptr;       // per kernel: blk_member [grid], blk_first [n], blk_count [n]
   Group grp[K_COUNT]{};
@@ -1210,7 +1245,9 @@ int kernel_blocks(int k, const Net& n, const ucac_batch_config& c) {
     case K_GEN: return gen_blocks(n);
     case K_BRANCH: return branch_blocks(n, c.branch_block);
     case K_UBAR: return ubar_blocks(n);
+    case K_BUS_PRE: return line_blocks(n);
     case K_BUS: return bus_blocks(n);
+    case K_BUS_POST: return line_blocks(n);
     case K_GEN_DUAL: return gen_dual_blocks(n);
     case K_FINALIZE: return 1;
     default: return lambda_blocks(n);
@@ -1265,14 +1302,16 @@ int batch_build(ucac_batch* b) {
       case K_GEN: launch_gen_grouped(g, b->grid[k], s); break;
       case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, s); break;
       case K_UBAR: launch_ubar_grouped(g, b->grid[k], s); break;
+      case K_BUS_PRE: launch_bus_pre_grouped(g, b->grid[k], s); break;
       case K_BUS: launch_bus_grouped(g, b->grid[k], s); break;
+      case K_BUS_POST: launch_bus_post_grouped(g, b->grid[k], s); break;
       case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], s); break;
       case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], s); break;
       default: launch_lambda_grouped(g, b->grid[k], s); break;
     }
     return hipGetLastError();
   };
-  const hipError_t le = enqueue_forked(launch, b->st, b->side, b->ev_fork, b->ev_join, &where);
+  const hipError_t le = enqueue_forked(launch, b->st, b->side, b->ev, &where);
   const hipError_t ce = hipStreamEndCapture(b->st, &b->graph);
   if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
   if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
@@ -1335,8 +1374,10 @@ int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* pa
   if (hipSetDevice(b->device) != hipSuccess) return bad(bfail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed"));
   if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev[2], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev[3], hipEventDisableTiming) != hipSuccess)
     return bad(bfail(nullptr, UCAC_E_DEVICE, "stream/event create failed"));
   std::vector<Member> hm(n);
   for (int k = 0; k < n; ++k) hm[k] = Member{b->m[k]->net, b->m[k]->st, b->m[k]->kp};
@@ -1510,8 +1551,8 @@ void ucac_batch_destroy(ucac_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_members) (void)hipFree(b->d_members);
-  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
   if (b->side) (void)hipStreamDestroy(b->side);
   if (b->st) (void)hipStreamDestroy(b->st);
   for (ucac_handle* h : b->m) ucac_destroy(h);

@@ -47,6 +47,7 @@ struct Net {
   const double *gs, *bs, *vmin, *vmax, *Pd, *Qd;
   const int* inc_start;  // [N+1] incidence of line ends per bus
   const int* inc_code;   // [2L] line*2 + side (0: from end, 1: to end)
+  const int* end_pos;    // [2L] position of line end line*2 + side in the incidence list
   const int* gen_start;  // [N+1]
   const int* gen_list;   // [G]
   // generators [G]
@@ -68,8 +69,10 @@ struct State {
   int* br_iters;                                               // [T][L]
   unsigned long long* br_count;  // [waves][5] running totals per wavefront of the line kernel (global lane / 64):
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks
-  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus and gen_dual
-  int red_ubar, red_bus, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
+  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus, bus_post, gen_dual
+  int red_ubar, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
+  double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres
+  double* bmu;                   // [2][T][N] balance multipliers of the bus QP
   float* x0;                     // [4][T][L] start points of the learned Newton start (FP32)
   float* log_feat;               // null, or [log_cap][20] logged inputs of the learned start
   float* log_targ;               // [log_cap][4] logged solutions

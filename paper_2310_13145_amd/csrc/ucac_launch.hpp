@@ -9,7 +9,9 @@ void launch_gen(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block);
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_bus_pre(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st);
@@ -21,22 +23,30 @@ struct Tuning {
   int dp_lanes = 64;
   int branch_block = 256;
 };
-enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS, K_GEN_DUAL, K_FINALIZE, K_LAMBDA, K_COUNT };
+enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS_PRE, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_LAMBDA, K_COUNT };
 int uc_dp_blocks(const Net& n, int dp_lanes);
 int gen_blocks(const Net& n);
 int branch_blocks(const Net& n, int block);
 int ubar_blocks(const Net& n);
 int bus_blocks(const Net& n);
+int line_blocks(const Net& n);
 int gen_dual_blocks(const Net& n);
 int lambda_blocks(const Net& n);
 void launch_uc_dp_grouped(const Group& g, int grid, int dp_lanes, int max_T, hipStream_t st);
 void launch_gen_grouped(const Group& g, int grid, hipStream_t st);
 void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st);
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st);
+void launch_bus_pre_grouped(const Group& g, int grid, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);
+void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st);
 void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st);
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st);
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st);
+
+// standalone UC dynamic programs on given tables (k_uc_dp.hip)
+size_t dp_tables_lds(int T, int lanes);
+void launch_dp_tables(const double* tab, int G, int T, const int* tu, const int* td, const int* u0, const int* lon,
+                      const int* loff, signed char* u_out, double* cost_out, int lanes, hipStream_t st);
 
 // learned warm start (k_mlp.hip)
 void mlp_launch_train(const MlpView& w, const float* X, const float* Yt, const int* idx, int nb, float inv_norm,

@@ -109,6 +109,8 @@ def lib():
         L.ucac_mlp_last_error.restype = C.c_char_p
         L.ucac_mlp_destroy.argtypes = [vp]
         L.ucac_mlp_destroy.restype = None
+        L.ucac_dp_batch.argtypes = [C.c_int32, C.c_int32] + [vp] * 8 + [C.c_int32, vp]
+        L.ucac_dp_batch.restype = C.c_int
         L.ucac_batch_create.argtypes = [C.POINTER(ucac_network), C.c_int32, C.POINTER(ucac_params), C.POINTER(vp)]
         L.ucac_batch_size.argtypes = [vp]
         L.ucac_batch_size.restype = C.c_int32
@@ -263,7 +265,7 @@ def ucac_get_branch_iters(h, n_line, T):
     return out
 
 
-KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus", "gen_dual", "finalize", "lambda")
+KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda")
 
 
 def ucac_kernel_times(h, n_iters):
@@ -519,3 +521,21 @@ class Batch:
         c = ucac_batch_config()
         _bcheck(lib().ucac_batch_get_config(self.b, C.byref(c)), self.b)
         return (c.dp_lanes, c.branch_block, c.order)
+
+
+def ucac_dp_batch(tab, min_up, min_dn, u0, hold_on, hold_off, lanes_per_unit=64, stream=None):
+    """G unit-commitment DPs on device tensors: tab [G, T, 2, 2] float64 (cuda),
+    the five int32 [G] tensors; returns (u_on [G, T] int8, cost [G] float64) on the
+    same device.  Enqueued on `stream` (a torch stream; default: the current one)."""
+    import torch
+    G, T = int(tab.shape[0]), int(tab.shape[1])
+    dev = tab.device
+    ints = [x.to(device=dev, dtype=torch.int32).contiguous() for x in (min_up, min_dn, u0, hold_on, hold_off)]
+    tab = tab.to(dtype=torch.float64).contiguous()
+    u = torch.empty((G, T), dtype=torch.int8, device=dev)
+    cost = torch.empty(G, dtype=torch.float64, device=dev)
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    rc = lib().ucac_dp_batch(G, T, C.c_void_p(tab.data_ptr()), *[C.c_void_p(x.data_ptr()) for x in ints],
+                             C.c_void_p(u.data_ptr()), C.c_void_p(cost.data_ptr()), int(lanes_per_unit), C.c_void_p(st))
+    _check(rc, None)
+    return u, cost

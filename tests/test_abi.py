@@ -106,3 +106,13 @@ def test_batch_validation(lib):
     p = ucac.ucac_params_default()
     assert lib.ucac_batch_create(None, 0, C.byref(p), C.byref(b)) == ucac.UCAC_E_INVAL
     assert ucac.BATCH_CANDIDATES[0] == (64, 256, 0) and len(ucac.BATCH_CANDIDATES) == 8
+
+
+def test_dp_batch_validation(lib):
+    """Argument checks of the standalone DP happen before any device work."""
+    assert lib.ucac_dp_batch(-1, 24, *([None] * 8), 64, None) == ucac.UCAC_E_INVAL
+    assert lib.ucac_dp_batch(10, 0, *([None] * 8), 64, None) == ucac.UCAC_E_INVAL
+    assert lib.ucac_dp_batch(10, 24, *([None] * 8), 32, None) == ucac.UCAC_E_INVAL
+    assert lib.ucac_dp_batch(10, 24, *([None] * 8), 64, None) == ucac.UCAC_E_INVAL  # null pointers
+    assert "null" in ucac.ucac_last_error(None)
+    assert lib.ucac_dp_batch(0, 24, *([None] * 8), 64, None) == ucac.UCAC_OK  # nothing to do
