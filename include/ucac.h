@@ -147,9 +147,11 @@ int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
  * the learned start this slot also times the network), relaxed commitments, bus
  * QP in three passes (line-end sums, bus solve with the generator-consensus
  * multipliers, line-end duplicates with the line multipliers),
- * coupling/commitment multipliers, control (residuals and inner/outer decision),
- * outer lambda update. */
-#define UCAC_N_KERNELS 10
+ * coupling/commitment multipliers, control (residuals and inner/outer decision).
+ * The step:outer multiplier update has no kernel of its own in an iteration: the
+ * kernels that own the rows apply it in the next iteration, and a call that ends
+ * with it pending applies it before returning. */
+#define UCAC_N_KERNELS 9
 
 /* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
  * with every kernel launched on its own and a HIP event recorded on the handle's
@@ -278,6 +280,14 @@ int ucac_batch_set_config(ucac_batch* b, const ucac_batch_config* c);
 int ucac_batch_get_config(const ucac_batch* b, ucac_batch_config* c);
 const char* ucac_batch_last_error(const ucac_batch* b);
 void ucac_batch_destroy(ucac_batch* b);
+
+/* Replace the parameters of a live handle (penalties, outer-loop and Newton
+ * settings, tol, warm_start 0/1) from the next iteration on; the iterate,
+ * multipliers and beta are kept (the multipliers are stored unscaled, so a
+ * changed penalty leaves them valid).  A learned start loaded with
+ * ucac_set_warmstart stays in use.  device cannot change.  UCAC_E_INVAL for
+ * invalid values (the handle is unchanged). */
+int ucac_set_params(ucac_handle* h, const ucac_params* params);
 
 /* Message of the last error on this handle (or of the last failed create when
  * h is NULL).  Valid until the next call on the handle. */

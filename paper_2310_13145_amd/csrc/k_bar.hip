@@ -27,7 +27,7 @@ namespace ucac {
 __device__ __forceinline__ void ubar_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int G = n.G, T = n.T, TG = T * G;
-  const int i = blk * BLOCK + threadIdx.x;
+  const int i = blk * UBLOCK + threadIdx.x;
   double dmax = 0.0;
   if (i < TG) {
     const int t = i / G, g = i - t * G;
@@ -113,18 +113,39 @@ __device__ __forceinline__ void ubar_body(const Net& n, const State& s, const Pa
   block_max_store<1>(v, which, s.red + (size_t)(s.red_ubar + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_ubar(Net n, State s, Par p) { ubar_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(UBLOCK) k_ubar(Net n, State s, Par p) { ubar_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(BLOCK) k_ubar_group(Group gr) {
+__global__ void __launch_bounds__(UBLOCK) k_ubar_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
   ubar_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-__device__ inline void zy_update(double* zr, double* yr, const double* lr, int k, double a, double rho, double beta,
-                                 double& rp, double& rin, double& zinf) {
-  const double z = -(lr[k] + yr[k] + rho * a) / (beta + rho);
+// A step:outer multiplier update decided by the previous iteration's control is
+// applied here, by the kernel that owns the row, just before the row's z update
+// (the multiplier is read nowhere else): lambda <- clamp(lambda + beta_prev z_prev).
+struct LamUpd {
+  bool on;
+  double b, lm;
+};
+
+__device__ inline LamUpd lambda_pending(const State& s, const Par& p) {
+  LamUpd u;
+  u.on = s.ctl->pending != 0;
+  u.b = s.ctl->beta_for_lambda;
+  u.lm = p.lambda_max;
+  return u;
+}
+
+__device__ inline void zy_update(double* zr, double* yr, double* lr, int k, double a, double rho, double beta,
+                                 const LamUpd& lu, double& rp, double& rin, double& zinf) {
+  double lam = lr[k];
+  if (lu.on) {
+    lam = clampd(lam + lu.b * zr[k], -lu.lm, lu.lm);
+    lr[k] = lam;
+  }
+  const double z = -(lam + yr[k] + rho * a) / (beta + rho);
   zr[k] = z;
   yr[k] = yr[k] + rho * (a + z);
   rp = nmax(rp, fabs(a));
@@ -178,12 +199,13 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
   const int TG = T * G;
-  const int idx = blk * BLOCK + threadIdx.x;
+  const int idx = blk * UBLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
     const int t = idx / N, i = idx - t * N;
     const double rpq = p.rho_pq, rva = p.rho_va, rc = p.rho_cpl;
     const double beta = s.sc[SC_BETA];
+    const LamUpd lu = lambda_pending(s, p);
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
@@ -253,8 +275,8 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
       rd = nmax(rd, nmax(fabs(pn - s.pb[k]), fabs(qn - s.qb[k])));
       s.pb[k] = pn;
       s.qb[k] = qn;
-      zy_update(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k, s.p[k] - pn, rpq, beta, rp, rin, zinf);
-      zy_update(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k, s.q[k] - qn, rpq, beta, rp, rin, zinf);
+      zy_update(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k, s.p[k] - pn, rpq, beta, lu, rp, rin, zinf);
+      zy_update(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k, s.q[k] - qn, rpq, beta, lu, rp, rin, zinf);
     }
   }
   const double v[4] = {rp, rin, rd, zinf};
@@ -271,6 +293,7 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
     const int t = idx / n.L, l = idx - t * n.L;
     const double rpq = p.rho_pq, rva = p.rho_va;
     const double beta = s.sc[SC_BETA];
+    const LamUpd lu = lambda_pending(s, p);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int code = 2 * l + side;
@@ -284,10 +307,10 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
       rd = nmax(rd, nmax(fabs(Pn - Pdup[k]), fabs(Qn - Qdup[k])));
       Pdup[k] = Pn;
       Qdup[k] = Qn;
-      zy_update(s.zB + d.rP * TL, s.yB + d.rP * TL, s.lB + d.rP * TL, k, d.fP - Pn, rpq, beta, rp, rin, zinf);
-      zy_update(s.zB + d.rQ * TL, s.yB + d.rQ * TL, s.lB + d.rQ * TL, k, d.fQ - Qn, rpq, beta, rp, rin, zinf);
-      zy_update(s.zB + d.rW * TL, s.yB + d.rW * TL, s.lB + d.rW * TL, k, d.v * d.v - wnew, rva, beta, rp, rin, zinf);
-      zy_update(s.zB + d.rT * TL, s.yB + d.rT * TL, s.lB + d.rT * TL, k, d.th - thnew, rva, beta, rp, rin, zinf);
+      zy_update(s.zB + d.rP * TL, s.yB + d.rP * TL, s.lB + d.rP * TL, k, d.fP - Pn, rpq, beta, lu, rp, rin, zinf);
+      zy_update(s.zB + d.rQ * TL, s.yB + d.rQ * TL, s.lB + d.rQ * TL, k, d.fQ - Qn, rpq, beta, lu, rp, rin, zinf);
+      zy_update(s.zB + d.rW * TL, s.yB + d.rW * TL, s.lB + d.rW * TL, k, d.v * d.v - wnew, rva, beta, lu, rp, rin, zinf);
+      zy_update(s.zB + d.rT * TL, s.yB + d.rT * TL, s.lB + d.rT * TL, k, d.th - thnew, rva, beta, lu, rp, rin, zinf);
     }
   }
   const double v[4] = {rp, rin, rd, zinf};
@@ -313,9 +336,9 @@ __global__ void __launch_bounds__(BLOCK) k_bus_post_group(Group gr) {
   bus_post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(UBLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
+__global__ void __launch_bounds__(UBLOCK) k_bus_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
@@ -325,11 +348,12 @@ __global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
 __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int G = n.G, TG = n.T * G;
-  const int i = blk * BLOCK + threadIdx.x;
+  const int i = blk * UBLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, zinf = 0.0;
   if (i < TG) {
     const int t = i / G, g = i - t * G;
     const double beta = s.sc[SC_BETA];
+    const LamUpd lu = lambda_pending(s, p);
     const double* nx_on = s.ub_nxt;
     const double* nx_su = s.ub_nxt + TG;
     const double* nx_sd = s.ub_nxt + 2 * TG;
@@ -351,7 +375,7 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
     for (int r = 0; r < 9; ++r) {
       const int row = RG_C1 + r;
       const double rho = r < 6 ? p.rho_cpl : p.rho_uc;
-      zy_update(s.zG + row * TG, s.yG + row * TG, s.lG + row * TG, i, a[r], rho, beta, rp, rin, zinf);
+      zy_update(s.zG + row * TG, s.yG + row * TG, s.lG + row * TG, i, a[r], rho, beta, lu, rp, rin, zinf);
     }
     s.ubon[i] = uon;
     s.ubsu[i] = usu;
@@ -362,25 +386,25 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
   block_max_store<3>(v, which, s.red + (size_t)(s.red_gdual + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(UBLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(BLOCK) k_gen_dual_group(Group gr) {
+__global__ void __launch_bounds__(UBLOCK) k_gen_dual_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
   gen_dual_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-int ubar_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
-int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
+int ubar_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
+int bus_blocks(const Net& n) { return (n.T * n.N + UBLOCK - 1) / UBLOCK; }
 int line_blocks(const Net& n) { return (n.T * n.L + BLOCK - 1) / BLOCK; }
-int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+int gen_dual_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
 
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
 void launch_bus_pre_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_pre_group, dim3(grid), dim3(BLOCK), 0, st, g);
@@ -389,19 +413,19 @@ void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
 
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TG = n.T * n.G;
   if (TG == 0) return;
-  hipLaunchKernelGGL(k_ubar, dim3((TG + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_ubar, dim3(ubar_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
 }
 
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;
   if (TN == 0) return;
-  hipLaunchKernelGGL(k_bus, dim3((TN + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
 }
 
 void launch_bus_pre(const Net& n, const State& s, const Par& p, hipStream_t st) {
@@ -419,7 +443,7 @@ void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st)
 void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TG = n.T * n.G;
   if (TG == 0) return;
-  hipLaunchKernelGGL(k_gen_dual, dim3((TG + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_gen_dual, dim3(gen_dual_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
 }
 
 }  // namespace ucac

@@ -5,7 +5,9 @@
 // then every later kernel of the handle returns at entry), or end of the inner
 // loop (max(r_in, r_d) <= max(tol/2, eps_in0 2^-k), or max_inner iterations),
 // in which case beta follows step:outer (times tau if ||z^k|| > theta ||z^{k-1}||)
-// and k_lambda applies lambda <- clamp(lambda + beta z) to every row.
+// and the multiplier update lambda <- clamp(lambda + beta z) is left pending: the
+// kernels that own the rows apply it in the next iteration just before their z
+// update, and k_lambda applies it to every row when a call ends with it pending.
 #include "ucac_launch.hpp"
 
 namespace ucac {
@@ -18,10 +20,21 @@ __device__ __forceinline__ void finalize_body(const Net& n, const State& s, cons
   Ctl* c = s.ctl;
   if (c->halt) return;
   // reduce the per-block maxima of this iteration's kernels
+  // up to 8 slots per thread per round, all loads issued before the first use
   double m[NACC] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < s.red_n; b += blockDim.x) {
+  constexpr int U = 8;
+  for (int b0 = threadIdx.x; b0 < s.red_n; b0 += U * (int)blockDim.x) {
+    double v[U][NACC];
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) m[k] = nmax(m[k], s.red[(size_t)b * NACC + k]);
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * (int)blockDim.x;
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) v[u][k] = b < s.red_n ? s.red[(size_t)b * NACC + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) m[k] = nmax(m[k], v[u][k]);
   }
   __shared__ double part[NACC][FIN_BLOCK / 64];
 #pragma unroll

@@ -16,7 +16,7 @@ namespace ucac {
 __device__ __forceinline__ void gen_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int TG = n.T * n.G;
-  const int i = blk * BLOCK + threadIdx.x;
+  const int i = blk * UBLOCK + threadIdx.x;
   if (i >= TG) return;
   const int t = i / n.G, g = i - t * n.G;
   const double rp = p.rho_pq, rc = p.rho_cpl;
@@ -63,25 +63,25 @@ __device__ __forceinline__ void gen_body(const Net& n, const State& s, const Par
   s.s[5 * TG + i] = fmax(0.0, -(pv + e6));
 }
 
-__global__ void __launch_bounds__(BLOCK) k_gen(Net n, State s, Par p) { gen_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(UBLOCK) k_gen(Net n, State s, Par p) { gen_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(BLOCK) k_gen_group(Group gr) {
+__global__ void __launch_bounds__(UBLOCK) k_gen_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
   gen_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-int gen_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+int gen_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
 
 void launch_gen_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_gen_group, dim3(grid), dim3(BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_gen_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
 
 void launch_gen(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TG = n.T * n.G;
   if (TG == 0) return;
-  hipLaunchKernelGGL(k_gen, dim3((TG + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_gen, dim3(gen_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
 }
 
 }  // namespace ucac

@@ -428,14 +428,14 @@ Par kernel_params(const ucac_params& p) {
 // finish (bus_post) and the coupling/commitment multipliers (gen_dual) touch
 // disjoint rows and run side by side again:
 //
-//   main: branch -> bus_pre --+-> bus --+-> bus_post ----+-> finalize -> lambda
+//   main: branch -> bus_pre --+-> bus --+-> bus_post ----+-> finalize
 //   side: uc_dp -> gen -> ubar +        +-> gen_dual ----+
 //
 // launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError();
 // ev[0..3]: capture-time fork/join events.
 template <class F>
 hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t* ev, const char** where) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize"};
   hipError_t e = hipSuccess;
   auto run = [&](int k, hipStream_t s) {
     if (e == hipSuccess) {
@@ -461,14 +461,13 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
   run(K_BUS_POST, main);
   link(side, main, ev[3]);
   run(K_FINALIZE, main);
-  run(K_LAMBDA, main);
   return e;
 }
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,     launch_bus_pre,
-      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize, launch_lambda};
+      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,    launch_bus_pre,
+      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize};
   auto launch = [&](int k, hipStream_t s) {
     fns[k](h->net, h->st, h->kp, s);
     return hipGetLastError();
@@ -478,10 +477,10 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,     launch_bus_pre,
-      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize, launch_lambda};
+      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,    launch_bus_pre,
+      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -516,6 +515,21 @@ int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
 int read_status(ucac_handle* h) {
   HIP_OR(h, hipMemcpyAsync(h->h_sc, h->st.sc, sizeof(double) * NSC, hipMemcpyDeviceToHost, h->stream));
   HIP_OR(h, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  return UCAC_OK;
+}
+
+// A call that ended right after an inner loop leaves the step:outer multiplier
+// update pending (the row owners apply it at the start of the next iteration):
+// apply it to every row now, so that the state a caller reads is complete.
+// Requires h_ctl to be current (read_status).
+int flush_lambda(ucac_handle* h) {
+  if (!h->h_ctl->pending) return UCAC_OK;
+  (void)hipGetLastError();
+  launch_lambda(h->net, h->st, h->kp, h->stream);
+  HIP_OR(h, hipGetLastError());
+  h->h_ctl->pending = 0;
+  HIP_OR(h, hipMemcpyAsync(&h->d_ctl->pending, &h->h_ctl->pending, sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_OR(h, hipStreamSynchronize(h->stream));
   return UCAC_OK;
 }
@@ -671,6 +685,8 @@ int ucac_step(ucac_handle* h, int32_t n_iters) {
   for (int i = 0; i < n_iters; ++i) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
   rc = read_status(h);
   if (rc) return rc;
+  rc = flush_lambda(h);
+  if (rc) return rc;
   return check_bad(h);
 }
 
@@ -699,6 +715,8 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
     done = h->h_sc[SC_CONV] != 0.0;
   }
   rc = read_status(h);
+  if (rc) return rc;
+  rc = flush_lambda(h);
   if (rc) return rc;
   if (iters_done) *iters_done = (int32_t)(h->h_sc[SC_ITER] - it0);
   rc = check_bad(h);
@@ -844,6 +862,8 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
   if (err != hipSuccess) return fail(h, UCAC_E_DEVICE, "timed iteration failed at %s: %s", where, hipGetErrorString(err));
   rc = read_status(h);
   if (rc) return rc;
+  rc = flush_lambda(h);
+  if (rc) return rc;
   return check_bad(h);
 }
 
@@ -895,6 +915,26 @@ MlpView mlp_view(const MlpBufs& b) {
   return v;
 }
 }  // namespace
+
+int ucac_set_params(ucac_handle* h, const ucac_params* params) {
+  if (!h || !params) return h ? fail(h, UCAC_E_INVAL, "null params") : UCAC_E_INVAL;
+  if (params->device != h->par.device) return fail(h, UCAC_E_INVAL, "params.device cannot change");
+  if (!(params->rho_pq > 0.0) || !(params->rho_va > 0.0) || !(params->rho_uc > 0.0) || !(params->rho_cpl > 0.0) ||
+      !(params->beta0 > 0.0) || !(params->tau > 0.0) || !(params->lambda_max > 0.0) || !(params->beta_max > 0.0) ||
+      !(params->mu_line > 0.0) || !(params->theta > 0.0) || !(params->newton_gtol >= 0.0) || !(params->eps_in0 >= 0.0) ||
+      !(params->tol > 0.0) || params->newton_max_iter < 0 || params->max_inner < 1 || params->warm_start < 0 ||
+      params->warm_start > 1 || !std::isfinite(params->rho_pq) || !std::isfinite(params->rho_va) ||
+      !std::isfinite(params->rho_uc) || !std::isfinite(params->rho_cpl) || !std::isfinite(params->mu_line))
+    return fail(h, UCAC_E_INVAL, "invalid params");
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  const bool learned = h->kp.warm_start == 2;
+  const MlpView mlp = h->kp.mlp;
+  h->par = *params;
+  h->kp = kernel_params(*params);
+  if (learned) { h->kp.warm_start = 2; h->kp.mlp = mlp; }
+  return build_graph(h);
+}
 
 int ucac_set_warmstart(ucac_handle* h, const float* weights, size_t n) {
   if (!h) return UCAC_E_INVAL;
@@ -956,6 +996,8 @@ int ucac_log_pairs(ucac_handle* h, int32_t n_iters, int32_t stride, float* feats
   if (err != hipSuccess) return fail(h, UCAC_E_DEVICE, "logging failed at %s: %s", where, hipGetErrorString(err));
   if (n_logged) *n_logged = m;
   rc = read_status(h);
+  if (rc) return rc;
+  rc = flush_lambda(h);
   if (rc) return rc;
   return check_bad(h);
 }
@@ -1342,6 +1384,22 @@ int batch_read(ucac_batch* b) {
   return UCAC_OK;
 }
 
+// Members whose last iteration left a multiplier update pending get it applied
+// (the single-instance flush kernel on the batch stream).  h_ctl must be current.
+int batch_flush(ucac_batch* b) {
+  bool any = false;
+  for (ucac_handle* h : b->m) {
+    if (!h->h_ctl->pending) continue;
+    any = true;
+    launch_lambda(h->net, h->st, h->kp, b->st);
+    BHIP_OR(b, hipGetLastError());
+    h->h_ctl->pending = 0;
+    BHIP_OR(b, hipMemcpyAsync(&h->d_ctl->pending, &h->h_ctl->pending, sizeof(int), hipMemcpyHostToDevice, b->st));
+  }
+  if (any) BHIP_OR(b, hipStreamSynchronize(b->st));
+  return UCAC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1410,7 +1468,9 @@ int ucac_batch_step(ucac_batch* b, int32_t n_iters) {
   int rc = batch_set_ctl(b, 0, b->m[0]->par.tol);
   if (rc) return rc;
   for (int i = 0; i < n_iters; ++i) BHIP_OR(b, hipGraphLaunch(b->exec, b->st));
-  return batch_read(b);
+  rc = batch_read(b);
+  if (rc) return rc;
+  return batch_flush(b);
 }
 
 int ucac_batch_solve(ucac_batch* b, double tol, int32_t max_iters, int32_t* iters_done, int32_t* converged) {
@@ -1442,6 +1502,8 @@ int ucac_batch_solve(ucac_batch* b, double tol, int32_t max_iters, int32_t* iter
     all = true;
     for (ucac_handle* h : b->m) all = all && h->h_sc[SC_CONV] != 0.0;
   }
+  rc = batch_flush(b);
+  if (rc) return rc;
   int n_conv = 0;
   for (int k = 0; k < n; ++k) {
     const bool cv = b->m[k]->h_sc[SC_CONV] != 0.0;

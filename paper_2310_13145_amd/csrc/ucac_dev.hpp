@@ -20,6 +20,9 @@ enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZIN
 enum { ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF, NACC };
 
 constexpr int BLOCK = 256;
+// Block size of the per-unit and per-bus kernels: they have few items (12,000 unit-
+// periods at 2,000 buses), so smaller blocks spread the loads over more CUs.
+constexpr int UBLOCK = 64;
 constexpr double TWO_PI = 6.283185307179586;
 
 // Device-resident control block of the iteration (never captured memsets: the

@@ -23,7 +23,8 @@ struct Tuning {
   int dp_lanes = 64;
   int branch_block = 256;
 };
-enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS_PRE, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_LAMBDA, K_COUNT };
+// K_ITER kernels per iteration; K_LAMBDA flushes a pending multiplier update after a call
+enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS_PRE, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
 int uc_dp_blocks(const Net& n, int dp_lanes);
 int gen_blocks(const Net& n);
 int branch_blocks(const Net& n, int block);

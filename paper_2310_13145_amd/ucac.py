@@ -98,6 +98,8 @@ def lib():
         L.ucac_solve_milestones.argtypes = [vp, vp]
         fp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_int64)
         L.ucac_set_warmstart.argtypes = [vp, vp, C.c_size_t]
+        L.ucac_set_params.argtypes = [vp, C.POINTER(ucac_params)]
+        L.ucac_set_params.restype = C.c_int
         L.ucac_log_pairs.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, i64p]
         L.ucac_mlp_create.argtypes = [C.c_int32, C.c_uint64, C.POINTER(vp)]
         L.ucac_mlp_set_weights.argtypes = [vp, vp, C.c_size_t]
@@ -265,7 +267,7 @@ def ucac_get_branch_iters(h, n_line, T):
     return out
 
 
-KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize", "lambda")
+KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize")
 
 
 def ucac_kernel_times(h, n_iters):
@@ -431,6 +433,17 @@ class Solver:
 
     def set_warmstart(self, weights):
         ucac_set_warmstart(self.h, weights)
+
+    def set_params(self, **over):
+        """Change parameters from the next iteration on (iterate and multipliers kept)."""
+        p = ucac_params()
+        C.memmove(C.byref(p), C.byref(self.params), C.sizeof(ucac_params))
+        for k, v in over.items():
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        _check(lib().ucac_set_params(self.h, C.byref(p)), self.h)
+        self.params = p
 
     def log_pairs(self, n_iters, stride=1, cap=None):
         N, L, G, T = self.dims

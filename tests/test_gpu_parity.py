@@ -241,3 +241,22 @@ def test_full_size_sampled():
     g.step(1)
     o.step(1)
     compare(g.get_state(), o.get_state(), inst, 1e-10, "cfg2 it41")
+
+
+def test_set_params_midway_matches_oracle():
+    """Penalties changed on a live handle (the multipliers are unscaled, so the iterate
+    carries over) give the oracle's trajectory under the same change."""
+    inst = synth.config_instance(1)
+    g, o = pair(inst)
+    g.step(20)
+    o.step(20)
+    new = dict(rho_pq=2.0 * g.params.rho_pq, rho_va=0.5 * g.params.rho_va, rho_cpl=2.0 * g.params.rho_cpl,
+               mu_line=2.0 * g.params.mu_line, rho_uc=3.0 * g.params.rho_uc)
+    g.set_params(**new)
+    o.set_params(**new)
+    g.step(30)
+    o.step(30)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, "after set_params")
+    with pytest.raises(ucac.UcacError):
+        g.set_params(rho_pq=-1.0)
+    g.step(1)  # the handle still works with its previous parameters
