@@ -35,15 +35,16 @@ FLOP_EVAL = 349      # value + gradient + 10-entry Hessian at one point (inactiv
 FLOP_TRIAL = 75      # value only at a trial point (what a rejected trial needs)
 FLOP_CG = 80         # one Steihaug-Toint CG iteration on the 4x4 system
 FLOP_NEWTON = 80     # per trust-region iteration: projection, predicted reduction, ratio, radius
-FLOP_LANE = 70       # per solve: targets from duplicates/multipliers, start, final flows, nu update
+FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, final flows, nu update,
+                     # the bus QP's per-end sums
 
 # Algorithmic HBM bytes per item, counted from the kernels' loads and stores (8 B per
 # double, each state array touched once per item; per-line/per-unit constants omitted):
-BYTES_BRANCH = 8 * 36 + 4   # x-bar (8), z, y (16), nu (2) in; x (4), flows (4), nu (2) out; iteration count
+BYTES_BRANCH = 8 * 52 + 12  # x-bar (8), z, y (16), nu (2) in; x (4), flows (4), nu (2) out; iteration count;
+                            # then the bus QP's per-end sums: z, y of 8 rows again (16 in, 8 out) and 2 positions
 BYTES_GEN = 8 * 29          # duplicates (5), z, y (16) in; p, q, six slacks out
 BYTES_UBAR = 8 * 40
 BYTES_GEN_DUAL = 8 * 66
-BYTES_BUS_PRE = 8 * 32 + 8  # per (line, t): both ends' flows, v, angle, z/y of 4 rows in; 8 sums out; positions
 BYTES_BUS_END = 8 * 4       # bus QP: the 4 sums of each incident line end
 BYTES_BUS_BUS = 8 * 8       # bus QP per (bus, t): wbar, thetabar in/out, 2 multipliers out, loads
 BYTES_BUS_GEN = 8 * 30      # bus QP per (unit, t): consensus and next-period ramp rows, duplicates out
@@ -346,7 +347,6 @@ def main():
     achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
     hbm = {
-        "bus_pre": {"bytes": lanes * BYTES_BUS_PRE, "ms": ktimes["bus_pre"]},
         "bus_post": {"bytes": lanes * BYTES_BUS_POST, "ms": ktimes["bus_post"]},
         "gen": {"bytes": G * T * BYTES_GEN, "ms": ktimes["gen"]},
         "ubar": {"bytes": G * T * BYTES_UBAR, "ms": ktimes["ubar"]},

@@ -8,9 +8,10 @@
 // step:opf_bar -- the diagonal QP of every bus-side duplicate subject to the P and Q
 //            balance equations (2x2 KKT system per bus; thetabar a weighted mean,
 //            zero at the reference bus) -- in three coalesced passes:
-// k_bus_pre  one lane per (line, t): per line end, the four quantities the bus sums
-//            need (P and Q targets, v^2 and angle centres), stored in the bus
-//            incidence (CSR) order so that each bus reads one contiguous range;
+//            (the line kernel, one lane per (line, t), ends by storing per line end
+//            the four quantities the bus sums need -- P and Q targets, v^2 and angle
+//            centres -- in the bus incidence (CSR) order, so that each bus reads
+//            one contiguous range)
 // k_bus      one lane per (bus, t): sums its ends' quantities in incidence order,
 //            solves the KKT system, writes wbar, thetabar and the two balance
 //            multipliers, and updates its generators' duplicates and rows G1, G2;
@@ -174,27 +175,6 @@ __device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, 
   return d;
 }
 
-__device__ __forceinline__ void bus_pre_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
-  if (s.ctl->halt) return;
-  const int TL = n.T * n.L;
-  const int idx = blk * BLOCK + threadIdx.x;
-  if (idx >= TL) return;
-  const int t = idx / n.L, l = idx - t * n.L;
-  const double rpq = p.rho_pq, rva = p.rho_va;
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int code = 2 * l + side;
-    const EndData d = load_end(n, s, t, TL, code, rpq);
-    const double zW = s.zB[d.rW * TL + d.k], yW = s.yB[d.rW * TL + d.k];
-    const double zT = s.zB[d.rT * TL + d.k], yT = s.yB[d.rT * TL + d.k];
-    double* o = s.ebuf + ((size_t)t * 2 * n.L + n.end_pos[code]) * 4;
-    o[0] = d.tP;
-    o[1] = d.tQ;
-    o[2] = d.v * d.v + zW + yW / rva;
-    o[3] = d.th + zT + yT / rva;
-  }
-}
-
 __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
@@ -210,16 +190,27 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
     const double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;
-    for (int e = e0; e < e1; ++e) {
-      const double* q = eb + (size_t)e * 4;
-      M11 += 1.0 / rpq;
-      aT -= q[0];
-      M22 += 1.0 / rpq;
-      bT -= q[1];
-      Ww += rva;
-      Sw += rva * q[2];
-      Wt += rva;
-      St += rva * q[3];
+    // four ends' sums loaded per round (all loads in flight), then added in order
+    for (int e = e0; e < e1; e += 4) {
+      double q[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double* src = eb + (size_t)(e + j < e1 ? e + j : e0) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[j][c] = src[c];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (e + j >= e1) break;
+        M11 += 1.0 / rpq;
+        aT -= q[j][0];
+        M22 += 1.0 / rpq;
+        bT -= q[j][1];
+        Ww += rva;
+        Sw += rva * q[j][2];
+        Wt += rva;
+        St += rva * q[j][3];
+      }
     }
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
     for (int e = g0; e < g1; ++e) {
@@ -318,15 +309,6 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_bus_pre(Net n, State s, Par p) { bus_pre_body(n, s, p, blockIdx.x, gridDim.x); }
-
-__global__ void __launch_bounds__(BLOCK) k_bus_pre_group(Group gr) {
-  const int mk = gr.blk_member[blockIdx.x];
-  const Member& M = gr.m[mk];
-  const int b0 = gr.blk_first[mk];
-  bus_pre_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
-}
-
 __global__ void __launch_bounds__(BLOCK) k_bus_post(Net n, State s, Par p) { bus_post_body(n, s, p, blockIdx.x, gridDim.x); }
 
 __global__ void __launch_bounds__(BLOCK) k_bus_post_group(Group gr) {
@@ -406,9 +388,6 @@ void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
-void launch_bus_pre_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_bus_pre_group, dim3(grid), dim3(BLOCK), 0, st, g);
-}
 void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
@@ -426,12 +405,6 @@ void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;
   if (TN == 0) return;
   hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
-}
-
-void launch_bus_pre(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  const int TL = n.T * n.L;
-  if (TL == 0) return;
-  hipLaunchKernelGGL(k_bus_pre, dim3(line_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
 void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st) {

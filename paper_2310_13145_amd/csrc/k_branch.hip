@@ -396,6 +396,25 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
     s.nuf[idx] = fmax(0.0, L.nu0 + L.mu * (f0 * f0 + f1 * f1 - L.rate2));
     s.nut[idx] = fmax(0.0, L.nu1 + L.mu * (f2 * f2 + f3 * f3 - L.rate2));
     s.br_iters[idx] = it;
+    {
+      // the per-end sums of the bus QP (step:opf_bar): P and Q targets and the v^2 and
+      // angle centres of both ends, stored at each end's place in its bus's incidence
+      // list, in plain IEEE arithmetic (no contraction) like the bus solve itself
+#pragma clang fp contract(off)
+      const int t = idx / n.L, l = idx - t * n.L;
+      double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;
+      const double fP[2] = {f0, f2}, fQ[2] = {f1, f3}, v[2] = {x[0], x[1]}, th[2] = {x[2], x[3]};
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int rP = side ? RB_PT : RB_PF, rQ = side ? RB_QT : RB_QF;
+        const int rW = side ? RB_WT : RB_WF, rT = side ? RB_TT : RB_TF;
+        double* o = eb + (size_t)n.end_pos[2 * l + side] * 4;
+        o[0] = fP[side] + s.zB[rP * TL + idx] + s.yB[rP * TL + idx] / L.rpq;
+        o[1] = fQ[side] + s.zB[rQ * TL + idx] + s.yB[rQ * TL + idx] / L.rpq;
+        o[2] = v[side] * v[side] + s.zB[rW * TL + idx] + s.yB[rW * TL + idx] / L.rva;
+        o[3] = th[side] + s.zB[rT * TL + idx] + s.yB[rT * TL + idx] / L.rva;
+      }
+    }
     if (s.log_feat && idx % s.log_stride == s.log_phase) {
       // (inputs, converged solution) pair for training the learned start
       const int slot = atomicAdd(s.log_count, 1);

@@ -428,14 +428,14 @@ Par kernel_params(const ucac_params& p) {
 // finish (bus_post) and the coupling/commitment multipliers (gen_dual) touch
 // disjoint rows and run side by side again:
 //
-//   main: branch -> bus_pre --+-> bus --+-> bus_post ----+-> finalize
-//   side: uc_dp -> gen -> ubar +        +-> gen_dual ----+
+//   main: branch ----------+-> bus --+-> bus_post ----+-> finalize
+//   side: uc_dp -> gen -> ubar        +-> gen_dual ----+
 //
 // launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError();
 // ev[0..3]: capture-time fork/join events.
 template <class F>
 hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t* ev, const char** where) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "finalize"};
   hipError_t e = hipSuccess;
   auto run = [&](int k, hipStream_t s) {
     if (e == hipSuccess) {
@@ -453,7 +453,6 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
   run(K_GEN, side);
   run(K_UBAR, side);
   run(K_BRANCH, main);
-  run(K_BUS_PRE, main);
   link(side, main, ev[1]);
   run(K_BUS, main);
   link(main, side, ev[2]);
@@ -466,8 +465,8 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,    launch_bus_pre,
-      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp,    launch_gen,      launch_branch,  launch_ubar,
+      launch_bus,      launch_bus_post, launch_gen_dual, launch_finalize};
   auto launch = [&](int k, hipStream_t s) {
     fns[k](h->net, h->st, h->kp, s);
     return hipGetLastError();
@@ -477,10 +476,10 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus_pre", "bus", "bus_post", "gen_dual", "finalize"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "finalize"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen,      launch_branch,   launch_ubar,    launch_bus_pre,
-      launch_bus,   launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp,    launch_gen,      launch_branch,  launch_ubar,
+      launch_bus,      launch_bus_post, launch_gen_dual, launch_finalize};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -1287,7 +1286,6 @@ int kernel_blocks(int k, const Net& n, const ucac_batch_config& c) {
     case K_GEN: return gen_blocks(n);
     case K_BRANCH: return branch_blocks(n, c.branch_block);
     case K_UBAR: return ubar_blocks(n);
-    case K_BUS_PRE: return line_blocks(n);
     case K_BUS: return bus_blocks(n);
     case K_BUS_POST: return line_blocks(n);
     case K_GEN_DUAL: return gen_dual_blocks(n);
@@ -1344,7 +1342,6 @@ int batch_build(ucac_batch* b) {
       case K_GEN: launch_gen_grouped(g, b->grid[k], s); break;
       case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, s); break;
       case K_UBAR: launch_ubar_grouped(g, b->grid[k], s); break;
-      case K_BUS_PRE: launch_bus_pre_grouped(g, b->grid[k], s); break;
       case K_BUS: launch_bus_grouped(g, b->grid[k], s); break;
       case K_BUS_POST: launch_bus_post_grouped(g, b->grid[k], s); break;
       case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], s); break;

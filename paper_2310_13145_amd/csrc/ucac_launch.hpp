@@ -9,7 +9,6 @@ void launch_gen(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block);
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st);
-void launch_bus_pre(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st);
@@ -24,7 +23,7 @@ struct Tuning {
   int branch_block = 256;
 };
 // K_ITER kernels per iteration; K_LAMBDA flushes a pending multiplier update after a call
-enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS_PRE, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
+enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
 int uc_dp_blocks(const Net& n, int dp_lanes);
 int gen_blocks(const Net& n);
 int branch_blocks(const Net& n, int block);
@@ -37,7 +36,6 @@ void launch_uc_dp_grouped(const Group& g, int grid, int dp_lanes, int max_T, hip
 void launch_gen_grouped(const Group& g, int grid, hipStream_t st);
 void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st);
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st);
-void launch_bus_pre_grouped(const Group& g, int grid, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);
 void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st);
 void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st);
