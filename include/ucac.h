@@ -147,8 +147,8 @@ int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
  * the learned start this slot also times the network; the line kernel also stores
  * the line-end sums of the bus QP), relaxed commitments, bus QP (bus solve with the
  * generator-consensus multipliers, then line-end duplicates with the line
- * multipliers),
- * coupling/commitment multipliers, control (residuals and inner/outer decision).
+ * multipliers), coupling/commitment multipliers, control (residuals and
+ * inner/outer decision).
  * The step:outer multiplier update has no kernel of its own in an iteration: the
  * kernels that own the rows apply it in the next iteration, and a call that ends
  * with it pending applies it before returning. */

@@ -179,7 +179,7 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
   const int TG = T * G;
-  const int idx = blk * UBLOCK + threadIdx.x;
+  const int idx = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
     const int t = idx / N, i = idx - t * N;
@@ -318,9 +318,9 @@ __global__ void __launch_bounds__(BLOCK) k_bus_post_group(Group gr) {
   bus_post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-__global__ void __launch_bounds__(UBLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(UBLOCK) k_bus_group(Group gr) {
+__global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(UBLOCK) k_bus_group(Group gr) {
 __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int G = n.G, TG = n.T * G;
-  const int i = blk * UBLOCK + threadIdx.x;
+  const int i = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, zinf = 0.0;
   if (i < TG) {
     const int t = i / G, g = i - t * G;
@@ -368,9 +368,9 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
   block_max_store<3>(v, which, s.red + (size_t)(s.red_gdual + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(UBLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
 
-__global__ void __launch_bounds__(UBLOCK) k_gen_dual_group(Group gr) {
+__global__ void __launch_bounds__(BLOCK) k_gen_dual_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
@@ -378,21 +378,21 @@ __global__ void __launch_bounds__(UBLOCK) k_gen_dual_group(Group gr) {
 }
 
 int ubar_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
-int bus_blocks(const Net& n) { return (n.T * n.N + UBLOCK - 1) / UBLOCK; }
+int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
 int line_blocks(const Net& n) { return (n.T * n.L + BLOCK - 1) / BLOCK; }
-int gen_dual_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
+int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
 
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(UBLOCK), 0, st, g);
 }
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(UBLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(UBLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {
@@ -404,7 +404,7 @@ void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;
   if (TN == 0) return;
-  hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
 void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st) {
@@ -416,7 +416,7 @@ void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st)
 void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TG = n.T * n.G;
   if (TG == 0) return;
-  hipLaunchKernelGGL(k_gen_dual, dim3(gen_dual_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
+  hipLaunchKernelGGL(k_gen_dual, dim3(gen_dual_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
 }  // namespace ucac

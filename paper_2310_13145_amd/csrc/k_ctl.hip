@@ -1,92 +1,25 @@
-// Inner/outer control of the two-level ADMM, decided on the device.
-//
-// k_finalize reduces the four residual maxima from the per-block slots, advances
-// the counters and decides: converged (solve mode: r_p <= tol and r_d <= tol,
-// then every later kernel of the handle returns at entry), or end of the inner
-// loop (max(r_in, r_d) <= max(tol/2, eps_in0 2^-k), or max_inner iterations),
-// in which case beta follows step:outer (times tau if ||z^k|| > theta ||z^{k-1}||)
-// and the multiplier update lambda <- clamp(lambda + beta z) is left pending: the
-// kernels that own the rows apply it in the next iteration just before their z
-// update, and k_lambda applies it to every row when a call ends with it pending.
+// The control step of an inner iteration (ucac_ctl.hpp) as a one-block kernel, and
+// the step:outer multiplier update applied to every row for a call that ends with
+// it pending (within an iteration the row owners apply it).
+#include "ucac_ctl.hpp"
 #include "ucac_launch.hpp"
 
 namespace ucac {
 
-// One block of finalize per instance reduces every per-block residual slot of the
-// iteration (hundreds to a few thousand): many threads keep many loads in flight.
-constexpr int FIN_BLOCK = 256;
-
-__device__ __forceinline__ void finalize_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
-  Ctl* c = s.ctl;
-  if (c->halt) return;
-  // reduce the per-block maxima of this iteration's kernels
-  // up to 8 slots per thread per round, all loads issued before the first use
-  double m[NACC] = {0.0, 0.0, 0.0, 0.0};
-  constexpr int U = 8;
-  for (int b0 = threadIdx.x; b0 < s.red_n; b0 += U * (int)blockDim.x) {
-    double v[U][NACC];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int b = b0 + u * (int)blockDim.x;
-#pragma unroll
-      for (int k = 0; k < NACC; ++k) v[u][k] = b < s.red_n ? s.red[(size_t)b * NACC + k] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int k = 0; k < NACC; ++k) m[k] = nmax(m[k], v[u][k]);
-  }
-  __shared__ double part[NACC][FIN_BLOCK / 64];
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) m[k] = wave_max(m[k]);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) part[k][threadIdx.x >> 6] = m[k];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m[k] = nmax(m[k], part[k][w]);
-    m[k] = nmax(m[k], part[k][0]);
-  }
-  double* sc = s.sc;
-  const double rp = m[ACC_RP], rin = m[ACC_RIN], rd = m[ACC_RD], zinf = m[ACC_ZINF];
-  sc[SC_RP] = rp;
-  sc[SC_RIN] = rin;
-  sc[SC_RD] = rd;
-  sc[SC_ZINF] = zinf;
-  sc[SC_ITER] += 1.0;
-  sc[SC_LIN] += 1.0;
-  c->pending = 0;
-  if (rp != rp || rin != rin || rd != rd || zinf != zinf) c->bad = 1;
-  c->ms_count += 1;
-  for (int m = 0; m < 3; ++m)
-    if (c->ms_iter[m] < 0 && rp <= c->ms_tol[m] && rd <= c->ms_tol[m]) c->ms_iter[m] = c->ms_count;
-  if (c->stop_at_tol && rp <= c->tol && rd <= c->tol) {
-    sc[SC_CONV] = 1.0;
-    c->halt = 1;
-    return;
-  }
-  const double eps = fmax(0.5 * c->tol, p.eps_in0 * ldexp(1.0, -(int)sc[SC_KOUT]));
-  if (fmax(rin, rd) <= eps || sc[SC_LIN] >= (double)p.max_inner) {
-    const double beta = sc[SC_BETA];
-    c->pending = 1;
-    c->beta_for_lambda = beta;
-    if (zinf > p.theta * sc[SC_ZPREV]) sc[SC_BETA] = fmin(p.tau * beta, p.beta_max);
-    sc[SC_ZPREV] = zinf;
-    sc[SC_KOUT] += 1.0;
-    sc[SC_LIN] = 0.0;
-  }
-}
-
-__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(n, s, p, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(s, p); }
 
 __global__ void __launch_bounds__(FIN_BLOCK) k_finalize_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
-  const int b0 = gr.blk_first[mk];
-  finalize_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+  finalize_body(M.s, M.p);
+}
+
+void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, n, s, p);
+}
+
+void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(FIN_BLOCK), 0, st, g);
 }
 
 __device__ __forceinline__ void lambda_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
@@ -110,9 +43,6 @@ __global__ void __launch_bounds__(BLOCK) k_lambda_group(Group gr) {
   lambda_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, n, s, p);
-}
 
 int lambda_blocks(const Net& n) {
   const long total = (long)NRB * n.T * n.L + (long)NRG * n.T * n.G;
@@ -126,9 +56,6 @@ void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st) {
   hipLaunchKernelGGL(k_lambda, dim3(lambda_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
-void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_group, dim3(grid), dim3(FIN_BLOCK), 0, st, g);
-}
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_lambda_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }

@@ -24,6 +24,11 @@ thread_local std::string g_create_error;
 // next chunk is already queued while the host reads the previous one.
 constexpr int SOLVE_CHUNK = 32;
 
+// Iterations captured in one graph: consecutive iterations inside a graph start
+// without the per-graph launch gap.  Iterations after convergence in solve mode
+// return at kernel entry, so running a few more is harmless.
+constexpr int GRAPH_UNROLL = 4;
+
 struct HostGen {
   std::vector<double> k2, k1, cnl, csu, csd;
   std::vector<int> u0;
@@ -45,8 +50,9 @@ struct ucac_handle {
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;      // pinned staging of the control block
   double* h_sc = nullptr;    // pinned staging of the scalars
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_u = nullptr;
+  hipGraphExec_t exec = nullptr;    // one iteration
+  hipGraphExec_t exec_u = nullptr;  // GRAPH_UNROLL iterations back to back
   hipEvent_t ev_poll = nullptr;
   hipStream_t side = nullptr;        // second capture stream of the iteration graph
   hipEvent_t ev[4] = {};             // capture-time fork/join events of the graph
@@ -449,10 +455,10 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
     if (e != hipSuccess && where && !*where) *where = "fork/join";
   };
   link(main, side, ev[0]);
+  run(K_BRANCH, main);  // captured first: the longest kernel is dispatched first
   run(K_UC_DP, side);
   run(K_GEN, side);
   run(K_UBAR, side);
-  run(K_BRANCH, main);
   link(side, main, ev[1]);
   run(K_BUS, main);
   link(main, side, ev[2]);
@@ -465,8 +471,7 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp,    launch_gen,      launch_branch,  launch_ubar,
-      launch_bus,      launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_bus_post, launch_gen_dual, launch_finalize};
   auto launch = [&](int k, hipStream_t s) {
     fns[k](h->net, h->st, h->kp, s);
     return hipGetLastError();
@@ -478,8 +483,7 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
   static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "finalize"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp,    launch_gen,      launch_branch,  launch_ubar,
-      launch_bus,      launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_bus_post, launch_gen_dual, launch_finalize};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -488,16 +492,30 @@ hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where,
 
 int build_graph(ucac_handle* h) {
   if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+  if (h->exec_u) { (void)hipGraphExecDestroy(h->exec_u); h->exec_u = nullptr; }
   if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
-  (void)hipGetLastError();
-  HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
-  const char* where = "";
-  const hipError_t le = enqueue_iteration(h, h->own, &where);
-  const hipError_t ce = hipStreamEndCapture(h->own, &h->graph);
-  if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
-  if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-  HIP_OR(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  if (h->graph_u) { (void)hipGraphDestroy(h->graph_u); h->graph_u = nullptr; }
+  for (int reps : {1, GRAPH_UNROLL}) {
+    (void)hipGetLastError();
+    HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
+    const char* where = "";
+    hipError_t le = hipSuccess;
+    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_iteration(h, h->own, &where);
+    hipGraph_t& g = reps == 1 ? h->graph : h->graph_u;
+    const hipError_t ce = hipStreamEndCapture(h->own, &g);
+    if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+    HIP_OR(h, hipGraphInstantiate(reps == 1 ? &h->exec : &h->exec_u, g, nullptr, nullptr, 0));
+  }
   return UCAC_OK;
+}
+
+// Enqueue n iterations: GRAPH_UNROLL at a time, the rest one by one.
+hipError_t launch_iterations(ucac_handle* h, int n) {
+  hipError_t e = hipSuccess;
+  for (; n >= GRAPH_UNROLL && e == hipSuccess; n -= GRAPH_UNROLL) e = hipGraphLaunch(h->exec_u, h->stream);
+  for (; n > 0 && e == hipSuccess; --n) e = hipGraphLaunch(h->exec, h->stream);
+  return e;
 }
 
 // Write the host-owned control fields (never inside a captured graph).
@@ -681,7 +699,7 @@ int ucac_step(ucac_handle* h, int32_t n_iters) {
   HIP_OR(h, hipSetDevice(h->par.device));
   int rc = set_ctl(h, 0, h->par.tol);
   if (rc) return rc;
-  for (int i = 0; i < n_iters; ++i) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
+  HIP_OR(h, launch_iterations(h, n_iters));
   rc = read_status(h);
   if (rc) return rc;
   rc = flush_lambda(h);
@@ -706,7 +724,7 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
   bool done = false;
   while (!done && launched < max_iters) {
     const int k = (max_iters - launched) < SOLVE_CHUNK ? (max_iters - launched) : SOLVE_CHUNK;
-    for (int i = 0; i < k; ++i) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
+    HIP_OR(h, launch_iterations(h, k));
     launched += k;
     rc = read_status(h);
     if (rc) return rc;
@@ -1227,7 +1245,9 @@ void ucac_destroy(ucac_handle* h) {
   (void)hipSetDevice(h->par.device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->exec_u) (void)hipGraphExecDestroy(h->exec_u);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->graph_u) (void)hipGraphDestroy(h->graph_u);
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
   for (hipEvent_t e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -1256,8 +1276,8 @@ struct ucac_batch {
   int grid[K_COUNT]{};
   int max_T = 1;
   ucac_batch_config cfg{64, 256, 0};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_u = nullptr;
+  hipGraphExec_t exec = nullptr, exec_u = nullptr;
   std::vector<int> it0;
   std::string err;
 };
@@ -1330,9 +1350,9 @@ int batch_build(ucac_batch* b) {
     g.blk_count = g.blk_first + n;
   }
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->exec_u) { (void)hipGraphExecDestroy(b->exec_u); b->exec_u = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-  (void)hipGetLastError();
-  BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  if (b->graph_u) { (void)hipGraphDestroy(b->graph_u); b->graph_u = nullptr; }
   const char* where = "";
   auto launch = [&](int k, hipStream_t s) {
     if (b->grid[k] == 0) return hipSuccess;
@@ -1350,12 +1370,25 @@ int batch_build(ucac_batch* b) {
     }
     return hipGetLastError();
   };
-  const hipError_t le = enqueue_forked(launch, b->st, b->side, b->ev, &where);
-  const hipError_t ce = hipStreamEndCapture(b->st, &b->graph);
-  if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
-  if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-  BHIP_OR(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  for (int reps : {1, GRAPH_UNROLL}) {
+    (void)hipGetLastError();
+    BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_forked(launch, b->st, b->side, b->ev, &where);
+    hipGraph_t& gr = reps == 1 ? b->graph : b->graph_u;
+    const hipError_t ce = hipStreamEndCapture(b->st, &gr);
+    if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
+    if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+    BHIP_OR(b, hipGraphInstantiate(reps == 1 ? &b->exec : &b->exec_u, gr, nullptr, nullptr, 0));
+  }
   return UCAC_OK;
+}
+
+hipError_t batch_launch_iterations(ucac_batch* b, int n) {
+  hipError_t e = hipSuccess;
+  for (; n >= GRAPH_UNROLL && e == hipSuccess; n -= GRAPH_UNROLL) e = hipGraphLaunch(b->exec_u, b->st);
+  for (; n > 0 && e == hipSuccess; --n) e = hipGraphLaunch(b->exec, b->st);
+  return e;
 }
 
 int batch_set_ctl(ucac_batch* b, int stop_at_tol, double tol) {
@@ -1464,7 +1497,7 @@ int ucac_batch_step(ucac_batch* b, int32_t n_iters) {
   for (ucac_handle* h : b->m) BHIP_OR(b, hipStreamSynchronize(h->stream));
   int rc = batch_set_ctl(b, 0, b->m[0]->par.tol);
   if (rc) return rc;
-  for (int i = 0; i < n_iters; ++i) BHIP_OR(b, hipGraphLaunch(b->exec, b->st));
+  BHIP_OR(b, batch_launch_iterations(b, n_iters));
   rc = batch_read(b);
   if (rc) return rc;
   return batch_flush(b);
@@ -1492,7 +1525,7 @@ int ucac_batch_solve(ucac_batch* b, double tol, int32_t max_iters, int32_t* iter
   bool all = false;
   while (!all && launched < max_iters) {
     const int c = std::min(SOLVE_CHUNK, max_iters - launched);
-    for (int i = 0; i < c; ++i) BHIP_OR(b, hipGraphLaunch(b->exec, b->st));
+    BHIP_OR(b, batch_launch_iterations(b, c));
     launched += c;
     rc = batch_read(b);
     if (rc) return rc;
@@ -1575,9 +1608,9 @@ int ucac_batch_autotune(ucac_batch* b, int32_t iters, ucac_batch_config* chosen,
     rc = batch_set_ctl(b, 0, b->m[0]->par.tol);
     if (rc) break;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, b->st);  // warm-up
+    if (e == hipSuccess) e = batch_launch_iterations(b, 2);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, b->st);
-    for (int i = 0; i < iters && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, b->st);
+    if (e == hipSuccess) e = batch_launch_iterations(b, iters);
     if (e == hipSuccess) e = hipEventRecord(e1, b->st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -1607,7 +1640,9 @@ void ucac_batch_destroy(ucac_batch* b) {
   (void)hipSetDevice(b->device);
   if (b->st) (void)hipStreamSynchronize(b->st);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec_u) (void)hipGraphExecDestroy(b->exec_u);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->graph_u) (void)hipGraphDestroy(b->graph_u);
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_members) (void)hipFree(b->d_members);
   for (hipEvent_t e : b->ev)

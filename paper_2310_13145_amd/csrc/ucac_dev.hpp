@@ -20,13 +20,15 @@ enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZIN
 enum { ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF, NACC };
 
 constexpr int BLOCK = 256;
-// Block size of the per-unit and per-bus kernels: they have few items (12,000 unit-
-// periods at 2,000 buses), so smaller blocks spread the loads over more CUs.
+// Block size of the generator and relaxed-commitment kernels: they have few items
+// (12,000 unit-periods at 2,000 buses), so smaller blocks spread the loads over more
+// CUs.  The others keep 256-thread blocks, which also keeps the number of residual
+// slots the control step reduces small.
 constexpr int UBLOCK = 64;
 constexpr double TWO_PI = 6.283185307179586;
 
-// Device-resident control block of the iteration (never captured memsets: the
-// finalize kernel clears the accumulators after reading them).
+// Device-resident control block of the iteration (written by the host between
+// calls, never by a memset inside the captured graph).
 struct Ctl {
   int halt;                      // set once converged in solve mode: every kernel returns at entry
   int stop_at_tol;               // solve mode
@@ -137,7 +139,7 @@ __device__ inline double wave_max(double v) {
 
 // Block-wide maxima of NV non-negative values, stored without atomics into this
 // block's slot of NACC doubles (slot[which[k]] = max of value k; the other entries
-// 0).  The finalize kernel reduces the slots of every block.  One slot per block
+// 0).  The control step reduces the slots of every block.  One slot per block
 // instead of device-scope atomics on a few shared addresses: those serialize at
 // the memory side of the chip, across its XCDs' separate L2 caches.
 template <int NV>
