@@ -157,7 +157,12 @@ int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
 /* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
  * with every kernel launched on its own and a HIP event recorded on the handle's
  * stream before and after it; avg_ms[k] (n_slots >= UCAC_N_KERNELS) receives the
- * mean device time of kernel k per iteration.  Synchronous. */
+ * mean device time of kernel k per iteration.  Those event pairs also count the
+ * latency between an event record and the next dispatch.  With n_slots >
+ * UCAC_N_KERNELS, avg_ms[UCAC_N_KERNELS] also receives the line kernel's mean
+ * duration taken from its own dispatch's begin and end timestamps (the figure
+ * a kernel trace reports; the learned start's network kernel is not in it).
+ * Synchronous. */
 int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots);
 
 /* Running totals of the line kernel's work since create or the last reset:

@@ -19,6 +19,7 @@
 // Gauss-Newton blocks and one weighted second-derivative block (all four flows
 // share the form a v_i^2 + b v_j^2 + v_i v_j (al cos d + be sin d)), so a full
 // evaluation costs about 200 flops.
+#include <hip/hip_ext.h>
 #include "ucac_launch.hpp"
 #include "ucac_mlp.hpp"
 
@@ -483,28 +484,43 @@ __global__ void __launch_bounds__(BLOCK) k_line_start(Net n, State s, Par p) {
 
 int branch_blocks(const Net& n, int block) { return (n.T * n.L + block - 1) / block; }
 
+// With e0 set, the launch carries its own start and stop events, which take the
+// dispatch's begin and end timestamps: the kernel's duration without the latency
+// of separate event records around it.
 template <int BS>
-static void launch_branch_bs(const Net* n, const State* s, const Par& p, const Group* g, int grid, int start, hipStream_t st) {
+static void launch_branch_bs(const Net* n, const State* s, const Par& p, const Group* g, int grid, int start, hipStream_t st,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (g) {
     if (start == START_LEARNED) hipLaunchKernelGGL((k_branch_group<START_LEARNED, BS>), dim3(grid), dim3(BS), 0, st, *g);
     else if (start == START_PREV) hipLaunchKernelGGL((k_branch_group<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *g);
     else hipLaunchKernelGGL((k_branch_group<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *g);
-  } else {
-    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch<START_LEARNED, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
-    else if (start == START_PREV) hipLaunchKernelGGL((k_branch<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
-    else hipLaunchKernelGGL((k_branch<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *n, *s, p);
+    return;
   }
+  void (*kern)(Net, State, Par) = start == START_LEARNED ? k_branch<START_LEARNED, BS>
+                                  : start == START_PREV  ? k_branch<START_PREV, BS>
+                                                         : k_branch<START_FLAT, BS>;
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, e0, e1, 0u, *n, *s, p);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, *n, *s, p);
 }
 
-void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block) {
+static void launch_branch_impl(const Net& n, const State& s, const Par& p, hipStream_t st, int block, hipEvent_t e0,
+                               hipEvent_t e1) {
   if (n.T * n.L == 0) return;
   if (p.warm_start == START_LEARNED) {
     const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
     hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
   }
   const int grid = branch_blocks(n, block);
-  if (block == 64) launch_branch_bs<64>(&n, &s, p, nullptr, grid, p.warm_start, st);
-  else launch_branch_bs<256>(&n, &s, p, nullptr, grid, p.warm_start, st);
+  if (block == 64) launch_branch_bs<64>(&n, &s, p, nullptr, grid, p.warm_start, st, e0, e1);
+  else launch_branch_bs<256>(&n, &s, p, nullptr, grid, p.warm_start, st, e0, e1);
+}
+
+void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block) {
+  launch_branch_impl(n, s, p, st, block, nullptr, nullptr);
+}
+
+void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  launch_branch_impl(n, s, p, st, 256, e0, e1);
 }
 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_branch_block(n, s, p, st, 256); }

@@ -855,26 +855,43 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
   int rc = set_ctl(h, 0, h->par.tol);
   if (rc) return rc;
   const int K = UCAC_N_KERNELS;
-  std::vector<hipEvent_t> ev((size_t)n_iters * (K + 1), nullptr);
+  const bool dispatch = n_slots > K;
+  // K + 1 markers per iteration, then (dispatch timing) the line kernel's own pair
+  const int E = K + 1 + (dispatch ? 2 : 0);
+  std::vector<hipEvent_t> ev((size_t)n_iters * E, nullptr);
   for (auto& e : ev) HIP_OR(h, hipEventCreate(&e));
   hipError_t err = hipSuccess;
   const char* where = "";
   for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
-    hipEvent_t* e = &ev[(size_t)it * (K + 1)];
+    hipEvent_t* e = &ev[(size_t)it * E];
     err = hipEventRecord(e[0], h->stream);
     for (int k = 0; k < K && err == hipSuccess; ++k) {
-      err = launch_one(h, k, h->stream, &where);
+      if (k == K_BRANCH && dispatch) {
+        launch_branch_timed(h->net, h->st, h->kp, h->stream, e[K + 1], e[K + 2]);
+        err = hipGetLastError();
+        if (err != hipSuccess) where = "branch";
+      } else {
+        err = launch_one(h, k, h->stream, &where);
+      }
       if (err == hipSuccess) err = hipEventRecord(e[k + 1], h->stream);
     }
   }
   if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
-  for (int k = 0; k < K; ++k) avg_ms[k] = 0.0;
-  for (int it = 0; it < n_iters && err == hipSuccess; ++it)
+  for (int k = 0; k < n_slots && k <= K; ++k) avg_ms[k] = 0.0;
+  for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
+    const hipEvent_t* e = &ev[(size_t)it * E];
     for (int k = 0; k < K && err == hipSuccess; ++k) {
       float ms = 0.0f;
-      err = hipEventElapsedTime(&ms, ev[(size_t)it * (K + 1) + k], ev[(size_t)it * (K + 1) + k + 1]);
+      err = hipEventElapsedTime(&ms, e[k], e[k + 1]);
       avg_ms[k] += ms / n_iters;
     }
+    // an empty instance launches no line kernel and leaves the pair unrecorded
+    if (dispatch && err == hipSuccess && h->T * h->L > 0) {
+      float ms = 0.0f;
+      err = hipEventElapsedTime(&ms, e[K + 1], e[K + 2]);
+      avg_ms[K] += ms / n_iters;
+    }
+  }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (err != hipSuccess) return fail(h, UCAC_E_DEVICE, "timed iteration failed at %s: %s", where, hipGetErrorString(err));
   rc = read_status(h);

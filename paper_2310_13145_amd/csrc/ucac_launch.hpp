@@ -8,6 +8,8 @@ void launch_uc_dp_lanes(const Net& n, const State& s, const Par& p, hipStream_t 
 void launch_gen(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block);
+// The line kernel at 256-lane blocks, timed by the dispatch's own start/stop events.
+void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st);

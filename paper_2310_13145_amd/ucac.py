@@ -271,10 +271,13 @@ KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "fin
 
 
 def ucac_kernel_times(h, n_iters):
-    """n_iters iterations launched kernel by kernel with HIP events; mean ms per kernel."""
-    out = np.zeros(len(KERNELS))
-    _check(lib().ucac_kernel_times(h, int(n_iters), _ptr(out), len(KERNELS)), h)
-    return dict(zip(KERNELS, out.tolist()))
+    """n_iters iterations launched kernel by kernel with HIP events; mean ms per kernel,
+    plus "branch_dispatch": the line kernel's mean from its dispatch's own timestamps."""
+    out = np.zeros(len(KERNELS) + 1)
+    _check(lib().ucac_kernel_times(h, int(n_iters), _ptr(out), len(out)), h)
+    d = dict(zip(KERNELS, out[:len(KERNELS)].tolist()))
+    d["branch_dispatch"] = float(out[len(KERNELS)])
+    return d
 
 
 def ucac_branch_counters(h, reset=False):

@@ -211,6 +211,23 @@ def test_determinism_and_resume_bit_exact():
     np.testing.assert_array_equal(a.get_state(), c.get_state())
 
 
+def test_kernel_times_same_iterates_as_step():
+    """The profiling entry point runs the same iterations as ucac_step, bit for bit, and
+    the line kernel's dispatch-timestamp duration lies inside the event pair around it."""
+    inst = synth.config_instance(1)
+    a = ucac.Solver(inst)
+    a.step(10)
+    mid = a.get_state()
+    a.step(23)
+    b = ucac.Solver(inst)
+    b.set_state(mid)
+    kt = b.kernel_times(23)
+    np.testing.assert_array_equal(a.get_state(), b.get_state())
+    assert set(kt) == set(ucac.KERNELS) | {"branch_dispatch"}
+    assert all(v > 0 for v in kt.values())
+    assert kt["branch_dispatch"] <= kt["branch"] * 1.001 + 1e-6
+
+
 def test_state_errors():
     inst = synth.config_instance(0)
     g = ucac.Solver(inst)
