@@ -340,10 +340,10 @@ def main():
     branch_dispatch_ms = ktimes.pop("branch_dispatch")
     prof_ms_per_step = sum(ktimes.values())
     lanes = T * L
-    # the kernel evaluates value, gradient and Hessian at every trial point and once more
-    # after a rejection; the method needs the full evaluation at the start and at accepted
-    # points and only the value at rejected ones, which is what is counted
-    full = cnt["evals"] - 2 * cnt["rejected"]
+    # the kernel evaluates value, gradient and Hessian at the start and at every trial
+    # point; the method needs the full evaluation at the start and at accepted points and
+    # only the value at rejected ones, which is what is counted
+    full = cnt["evals"] - cnt["rejected"]
     flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
                         cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
     br_s = branch_dispatch_ms * 1e-3

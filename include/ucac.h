@@ -167,7 +167,8 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
 
 /* Running totals of the line kernel's work since create or the last reset:
  * out[0] evaluations of value, gradient and Hessian (one at the start of each
- * solve, one at every trial point, one more after each rejected trial), out[1]
+ * solve and one at every trial point; after a rejected trial the gradient and
+ * Hessian of the current point are reused, not formed again), out[1]
  * rejected trial steps, out[2] CG iterations, out[3] Newton iterations, out[4]
  * learned starts that fell back to the flat start (out has 5 slots).  reset != 0
  * zeroes them after reading. */

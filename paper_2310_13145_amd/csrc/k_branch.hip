@@ -176,6 +176,21 @@ __device__ inline double dot(const double (&a)[4], const double (&b)[4]) {
   return (a[0] * b[0] + a[1] * b[1]) + (a[2] * b[2] + a[3] * b[3]);
 }
 
+// Refined reciprocal of d > 0: the hardware estimate plus two Newton steps.
+__device__ inline double qrcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// The step length tau >= 0 with ||z + tau d|| = delta (||z|| < delta).  The reciprocal
+// of d.d is formed beside the square root rather than after it.
+__device__ inline double to_boundary(const double (&z)[4], const double (&d)[4], double delta2) {
+  const double zd = dot(z, d), dd = dot(d, d), zz = dot(z, z);
+  const double inv = qrcp(dd);
+  return (-zd + sqrt(zd * zd + dd * (delta2 - zz))) * inv;
+}
+
 // Steihaug-Toint CG on the free variables (mask fr), radius delta.
 __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const double (&fr)[4], int nf, double delta,
                                 double (&out)[4], int& cg_its) {
@@ -195,9 +210,8 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 #pragma unroll
     for (int i = 0; i < 4; ++i) zn[i] = z[i] + alpha * d[i];
     if (dHd <= 0.0 || dot(zn, zn) >= delta2) {
-      // to the boundary along d: ||z + tau d|| = delta
-      const double zd = dot(z, d), dd = dot(d, d), zz = dot(z, z);
-      const double tau = (-zd + sqrt(zd * zd + dd * (delta2 - zz))) / dd;
+      // to the boundary along d
+      const double tau = to_boundary(z, d, delta2);
 #pragma unroll
       for (int i = 0; i < 4; ++i) out[i] = z[i] + tau * d[i];
       return;
@@ -215,12 +229,36 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
   for (int i = 0; i < 4; ++i) out[i] = z[i];
 }
 
+// Gradient and Hessian at the current iterate, kept in LDS so that a rejected trial
+// (whose own gradient and Hessian were formed with its value) costs no second
+// evaluation: slot k of the lane's 14 values at gh[k][lane] (conflict-free).
+template <int BS>
+struct GHSave {
+  double (*gh)[BS];
+  __device__ void store(const double (&g)[4], const Sym4& H) const {
+    const int t = threadIdx.x;
+    gh[0][t] = g[0]; gh[1][t] = g[1]; gh[2][t] = g[2]; gh[3][t] = g[3];
+    gh[4][t] = H.h00; gh[5][t] = H.h01; gh[6][t] = H.h02; gh[7][t] = H.h03; gh[8][t] = H.h11;
+    gh[9][t] = H.h12; gh[10][t] = H.h13; gh[11][t] = H.h22; gh[12][t] = H.h23; gh[13][t] = H.h33;
+  }
+  __device__ void load(double (&g)[4], Sym4& H) const {
+    const int t = threadIdx.x;
+    g[0] = gh[0][t]; g[1] = gh[1][t]; g[2] = gh[2][t]; g[3] = gh[3][t];
+    H.h00 = gh[4][t]; H.h01 = gh[5][t]; H.h02 = gh[6][t]; H.h03 = gh[7][t]; H.h11 = gh[8][t];
+    H.h12 = gh[9][t]; H.h13 = gh[10][t]; H.h22 = gh[11][t]; H.h23 = gh[12][t]; H.h33 = gh[13][t];
+  }
+};
+
 // Projected trust-region Newton from x (in place).  Returns the iterations taken;
 // conv is set when it stopped at the projected-gradient tolerance.  There is one
 // evaluation site: value, gradient and Hessian are formed at every trial point in
-// one pass (nearly every trial is accepted), and after a rejected trial at x again.
+// one pass (nearly every trial is accepted); after a rejection the gradient and
+// Hessian at x come back from LDS.  The ratio tests compare the actual decrease
+// with multiples of the predicted one (pred > 0), which decides as the quotient
+// does without a division on the dependency chain.
+template <int BS>
 __device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
-                             int& n_eval, int& n_rej, int& n_cg, bool& conv) {
+                             const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, bool& conv) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
   double g[4], xe[4];
@@ -235,23 +273,26 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
   for (;;) {
     const double Fe = evaluate(L, xe, g, H);
     ++n_eval;
+    bool accept = true;
     if (trial) {
-      const double ratio = pred > 0.0 ? (pred <= 1e-12 * fabs(F) ? 1.0 : (F - Fe) / pred) : -1.0;
-      if (ratio < 0.25) delta = 0.25 * snorm;
-      else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
+      // ratio = (F - Fe) / pred if pred > 0 (1 if pred is at the rounding level of F), else -1
+      const double ared = F - Fe;
+      const bool pos = pred > 0.0, noise = pred <= 1e-12 * fabs(F);
+      const bool lt_quarter = !pos || (!noise && ared < 0.25 * pred);
+      const bool gt_3quarter = pos && (noise || ared > 0.75 * pred);
+      accept = pos && (noise || ared >= 1e-4 * pred);
+      if (lt_quarter) delta = 0.25 * snorm;
+      else if (gt_3quarter && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
       trial = false;
-      if (ratio >= 1e-4) {
+    }
+    if (accept) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = xe[i];
-        F = Fe;
-      } else {
-        ++n_rej;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xe[i] = x[i];
-        continue;  // gradient and Hessian at x again
-      }
-    } else {
+      for (int i = 0; i < 4; ++i) x[i] = xe[i];
       F = Fe;
+      save.store(g, H);
+    } else {
+      ++n_rej;
+      save.load(g, H);
     }
     if (it >= p.newton_max_iter) break;
     double fr[4];
@@ -360,6 +401,8 @@ enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
 template <int START, int BS>
 __device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
   if (s.ctl->halt) return;
+  __shared__ double gh_lds[14][BS];
+  const GHSave<BS> save{gh_lds};
   const int TL = n.T * n.L;
   const int idx = blk * BS + threadIdx.x;
   const bool active = idx < TL;
@@ -382,11 +425,11 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   if (active) {
     bool conv;
-    it = newton(L, lo, hi, x, p, n_eval, n_rej, n_cg, conv);
+    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, conv);
     if (START == START_LEARNED && !conv) {
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton(L, lo, hi, x, p, n_eval, n_rej, n_cg, conv);
+      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, conv);
     }
     double S, C;
     sincos(x[2] - x[3], &S, &C);
