@@ -350,11 +350,10 @@ def main():
     achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
     hbm = {
-        "bus_post": {"bytes": lanes * BYTES_BUS_POST, "ms": ktimes["bus_post"]},
+        "post": {"bytes": lanes * BYTES_BUS_POST + G * T * BYTES_GEN_DUAL, "ms": ktimes["post"]},
         "gen": {"bytes": G * T * BYTES_GEN, "ms": ktimes["gen"]},
         "ubar": {"bytes": G * T * BYTES_UBAR, "ms": ktimes["ubar"]},
         "bus": {"bytes": bytes_bus, "ms": ktimes["bus"]},
-        "gen_dual": {"bytes": G * T * BYTES_GEN_DUAL, "ms": ktimes["gen_dual"]},
         "branch": {"bytes": lanes * BYTES_BRANCH, "ms": ktimes["branch"]},
     }
     for v in hbm.values():

@@ -146,13 +146,13 @@ int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
  * reports them: UC dynamic program, generators, lines (trust-region Newton; with
  * the learned start this slot also times the network; the line kernel also stores
  * the line-end sums of the bus QP), relaxed commitments, bus QP (bus solve with the
- * generator-consensus multipliers, then line-end duplicates with the line
- * multipliers), coupling/commitment multipliers, control (residuals and
- * inner/outer decision).
+ * generator-consensus multipliers), the line-end duplicates with the line
+ * multipliers together with the coupling/commitment multipliers (one launch),
+ * control (residuals and inner/outer decision).
  * The step:outer multiplier update has no kernel of its own in an iteration: the
  * kernels that own the rows apply it in the next iteration, and a call that ends
  * with it pending applies it before returning. */
-#define UCAC_N_KERNELS 8
+#define UCAC_N_KERNELS 7
 
 /* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
  * with every kernel launched on its own and a HIP event recorded on the handle's

@@ -309,15 +309,6 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_bus_post(Net n, State s, Par p) { bus_post_body(n, s, p, blockIdx.x, gridDim.x); }
-
-__global__ void __launch_bounds__(BLOCK) k_bus_post_group(Group gr) {
-  const int mk = gr.blk_member[blockIdx.x];
-  const Member& M = gr.m[mk];
-  const int b0 = gr.blk_first[mk];
-  bus_post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
-}
-
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
 
 __global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
@@ -368,19 +359,29 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
   block_max_store<3>(v, which, s.red + (size_t)(s.red_gdual + blk) * NACC);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_gen_dual(Net n, State s, Par p) { gen_dual_body(n, s, p, blockIdx.x, gridDim.x); }
+// step:opf_bar's line-end finish and the generator rows' multipliers in one launch:
+// the first line_blocks blocks finish the line ends (bus_post_body), the rest update
+// the coupling and commitment rows (gen_dual_body).  Both need only the bus solve,
+// touch disjoint rows and write their own residual slots; one launch costs one
+// kernel boundary on the iteration's critical path instead of a fork and a join.
+__device__ __forceinline__ void post_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+  const int nbp = line_blocks(n);
+  if (blk < nbp) bus_post_body(n, s, p, blk, nbp);
+  else gen_dual_body(n, s, p, blk - nbp, nblk - nbp);
+}
 
-__global__ void __launch_bounds__(BLOCK) k_gen_dual_group(Group gr) {
+__global__ void __launch_bounds__(BLOCK) k_post(Net n, State s, Par p) { post_body(n, s, p, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(BLOCK) k_post_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
   const int b0 = gr.blk_first[mk];
-  gen_dual_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
+  post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
 int ubar_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
 int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
-int line_blocks(const Net& n) { return (n.T * n.L + BLOCK - 1) / BLOCK; }
-int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+int post_blocks(const Net& n) { return line_blocks(n) + gen_dual_blocks(n); }
 
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(UBLOCK), 0, st, g);
@@ -388,11 +389,8 @@ void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
-void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_bus_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
-}
-void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_gen_dual_group, dim3(grid), dim3(BLOCK), 0, st, g);
+void launch_post_grouped(const Group& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {
@@ -407,16 +405,10 @@ void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
 }
 
-void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  const int TL = n.T * n.L;
-  if (TL == 0) return;
-  hipLaunchKernelGGL(k_bus_post, dim3(line_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
-}
-
-void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  const int TG = n.T * n.G;
-  if (TG == 0) return;
-  hipLaunchKernelGGL(k_gen_dual, dim3(gen_dual_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
+void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const int nb = post_blocks(n);
+  if (nb == 0) return;
+  hipLaunchKernelGGL(k_post, dim3(nb), dim3(BLOCK), 0, st, n, s, p);
 }
 
 }  // namespace ucac

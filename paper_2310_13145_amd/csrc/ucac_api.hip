@@ -55,7 +55,7 @@ struct ucac_handle {
   hipGraphExec_t exec_u = nullptr;  // GRAPH_UNROLL iterations back to back
   hipEvent_t ev_poll = nullptr;
   hipStream_t side = nullptr;        // second capture stream of the iteration graph
-  hipEvent_t ev[4] = {};             // capture-time fork/join events of the graph
+  hipEvent_t ev[2] = {};             // capture-time fork/join events of the graph
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
@@ -430,18 +430,17 @@ Par kernel_params(const ucac_params& p) {
 // Enqueue one inner iteration for capture.  step:uc and the generator part of
 // step:opf do not depend on the line kernel, and step:uc_bar depends only on them
 // (it reads the previous pbar, which the bus kernel then overwrites), so these three
-// run on a side stream beside the line kernel.  After the bus QP, the line-side
-// finish (bus_post) and the coupling/commitment multipliers (gen_dual) touch
-// disjoint rows and run side by side again:
+// run on a side stream beside the line kernel.  After the bus QP, one launch
+// finishes the line ends and updates the coupling/commitment multipliers:
 //
-//   main: branch ----------+-> bus --+-> bus_post ----+-> finalize
-//   side: uc_dp -> gen -> ubar        +-> gen_dual ----+
+//   main: branch ----------+-> bus -> post -> finalize
+//   side: uc_dp -> gen -> ubar
 //
 // launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError();
-// ev[0..3]: capture-time fork/join events.
+// ev[0..1]: capture-time fork/join events.
 template <class F>
 hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t* ev, const char** where) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "finalize"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "post", "finalize"};
   hipError_t e = hipSuccess;
   auto run = [&](int k, hipStream_t s) {
     if (e == hipSuccess) {
@@ -461,17 +460,14 @@ hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent
   run(K_UBAR, side);
   link(side, main, ev[1]);
   run(K_BUS, main);
-  link(main, side, ev[2]);
-  run(K_GEN_DUAL, side);
-  run(K_BUS_POST, main);
-  link(side, main, ev[3]);
+  run(K_POST, main);
   run(K_FINALIZE, main);
   return e;
 }
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_post, launch_finalize};
   auto launch = [&](int k, hipStream_t s) {
     fns[k](h->net, h->st, h->kp, s);
     return hipGetLastError();
@@ -481,9 +477,9 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "bus_post", "gen_dual", "finalize"};
+  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "post", "finalize"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_bus_post, launch_gen_dual, launch_finalize};
+      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_post, launch_finalize};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -1286,7 +1282,7 @@ struct ucac_batch {
   int warm_start = 0;
   std::vector<ucac_handle*> m;
   hipStream_t st = nullptr, side = nullptr;
-  hipEvent_t ev[4] = {};
+  hipEvent_t ev[2] = {};
   Member* d_members = nullptr;
   int* d_tables = nullptr;       // per kernel: blk_member [grid], blk_first [n], blk_count [n]
   Group grp[K_COUNT]{};
@@ -1324,8 +1320,7 @@ int kernel_blocks(int k, const Net& n, const ucac_batch_config& c) {
     case K_BRANCH: return branch_blocks(n, c.branch_block);
     case K_UBAR: return ubar_blocks(n);
     case K_BUS: return bus_blocks(n);
-    case K_BUS_POST: return line_blocks(n);
-    case K_GEN_DUAL: return gen_dual_blocks(n);
+    case K_POST: return post_blocks(n);
     case K_FINALIZE: return 1;
     default: return lambda_blocks(n);
   }
@@ -1380,8 +1375,7 @@ int batch_build(ucac_batch* b) {
       case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, s); break;
       case K_UBAR: launch_ubar_grouped(g, b->grid[k], s); break;
       case K_BUS: launch_bus_grouped(g, b->grid[k], s); break;
-      case K_BUS_POST: launch_bus_post_grouped(g, b->grid[k], s); break;
-      case K_GEN_DUAL: launch_gen_dual_grouped(g, b->grid[k], s); break;
+      case K_POST: launch_post_grouped(g, b->grid[k], s); break;
       case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], s); break;
       default: launch_lambda_grouped(g, b->grid[k], s); break;
     }
@@ -1480,9 +1474,7 @@ int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* pa
   if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev[2], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev[3], hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess)
     return bad(bfail(nullptr, UCAC_E_DEVICE, "stream/event create failed"));
   std::vector<Member> hm(n);
   for (int k = 0; k < n; ++k) hm[k] = Member{b->m[k]->net, b->m[k]->st, b->m[k]->kp};

@@ -11,10 +11,11 @@
 // apply it in the next iteration just before their z update, and k_lambda applies
 // it to every row when a call ends with it pending.
 //
-// It runs as its own one-block kernel after the iteration's last two kernels
-// (bus_post and gen_dual, which run side by side).  Running it in the last block of
-// those two instead (a completion count per iteration) saved 1 % at 2,000 buses and
-// cost 25 % at 10,000: one block pulling every slot across the XCDs is slow.
+// It runs as its own one-block kernel after the iteration's last kernel (the
+// line-end finish and generator-row multipliers).  Running it in the last block to
+// finish of that work instead (a completion count per iteration) saved 1 % at 2,000
+// buses and cost 25 % at 10,000: one block pulling every slot across the XCDs is
+// slow.
 #pragma once
 #include "ucac_dev.hpp"
 

@@ -60,6 +60,10 @@ struct Net {
   const int *tu, *td, *u0, *lon, *loff;
 };
 
+// Blocks of BLOCK threads over the (line, t) and (generator, t) items.
+__host__ __device__ inline int line_blocks(const Net& n) { return (n.T * n.L + BLOCK - 1) / BLOCK; }
+__host__ __device__ inline int gen_dual_blocks(const Net& n) { return (n.T * n.G + BLOCK - 1) / BLOCK; }
+
 struct State {
   double *vf, *vt, *thf, *tht, *pf, *qf, *pt, *qt, *nuf, *nut;  // [T][L]
   double *p, *q, *s;                                           // s: [6][T][G]
@@ -74,7 +78,7 @@ struct State {
   int* br_iters;                                               // [T][L]
   unsigned long long* br_count;  // [waves][5] running totals per wavefront of the line kernel (global lane / 64):
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks
-  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus, bus_post, gen_dual
+  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus and post (line ends, then generator rows)
   int red_ubar, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
   double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres
   double* bmu;                   // [2][T][N] balance multipliers of the bus QP

@@ -12,8 +12,7 @@ void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t
 void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
-void launch_bus_post(const Net& n, const State& s, const Par& p, hipStream_t st);
-void launch_gen_dual(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st);
 
@@ -25,22 +24,20 @@ struct Tuning {
   int branch_block = 256;
 };
 // K_ITER kernels per iteration; K_LAMBDA flushes a pending multiplier update after a call
-enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS, K_BUS_POST, K_GEN_DUAL, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
+enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS, K_POST, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
 int uc_dp_blocks(const Net& n, int dp_lanes);
 int gen_blocks(const Net& n);
 int branch_blocks(const Net& n, int block);
 int ubar_blocks(const Net& n);
 int bus_blocks(const Net& n);
-int line_blocks(const Net& n);
-int gen_dual_blocks(const Net& n);
+int post_blocks(const Net& n);
 int lambda_blocks(const Net& n);
 void launch_uc_dp_grouped(const Group& g, int grid, int dp_lanes, int max_T, hipStream_t st);
 void launch_gen_grouped(const Group& g, int grid, hipStream_t st);
 void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st);
 void launch_ubar_grouped(const Group& g, int grid, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);
-void launch_bus_post_grouped(const Group& g, int grid, hipStream_t st);
-void launch_gen_dual_grouped(const Group& g, int grid, hipStream_t st);
+void launch_post_grouped(const Group& g, int grid, hipStream_t st);
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st);
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st);
 
