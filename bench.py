@@ -45,7 +45,9 @@ FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, fi
 BYTES_BRANCH = 8 * 52 + 12  # x-bar (8), z, y (16), nu (2) in; x (4), flows (4), nu (2) out; iteration count;
                             # then the bus QP's per-end sums: z, y of 8 rows again (16 in, 8 out) and 2 positions
 BYTES_GEN = 8 * 29          # duplicates (5), z, y (16) in; p, q, six slacks out
+BYTES_DP = 8 * 12           # relaxed commitments (3), z, y of U1..U3 (6) in; u_on, u_su, u_sd out
 BYTES_UBAR = 8 * 40
+BYTES_UNITS = BYTES_GEN + BYTES_DP + BYTES_UBAR  # the unit kernel per (unit, t)
 BYTES_GEN_DUAL = 8 * 66
 BYTES_BUS_END = 8 * 4       # bus QP: the 4 sums of each incident line end
 BYTES_BUS_BUS = 8 * 8       # bus QP per (bus, t): wbar, thetabar in/out, 2 multipliers out, loads
@@ -351,8 +353,7 @@ def main():
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
     hbm = {
         "post": {"bytes": lanes * BYTES_BUS_POST + G * T * BYTES_GEN_DUAL, "ms": ktimes["post"]},
-        "gen": {"bytes": G * T * BYTES_GEN, "ms": ktimes["gen"]},
-        "ubar": {"bytes": G * T * BYTES_UBAR, "ms": ktimes["ubar"]},
+        "units": {"bytes": G * T * BYTES_UNITS, "ms": ktimes["units"]},
         "bus": {"bytes": bytes_bus, "ms": ktimes["bus"]},
         "branch": {"bytes": lanes * BYTES_BRANCH, "ms": ktimes["branch"]},
     }

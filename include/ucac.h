@@ -143,16 +143,17 @@ int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes);
 int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
 
 /* Number of kernels in one inner iteration, in the order ucac_kernel_times
- * reports them: UC dynamic program, generators, lines (trust-region Newton; with
+ * reports them: the unit side (per generator: the generator update, the UC
+ * dynamic program and the relaxed commitments), lines (trust-region Newton; with
  * the learned start this slot also times the network; the line kernel also stores
- * the line-end sums of the bus QP), relaxed commitments, bus QP (bus solve with the
+ * the line-end sums of the bus QP), bus QP (bus solve with the
  * generator-consensus multipliers), the line-end duplicates with the line
  * multipliers together with the coupling/commitment multipliers (one launch),
  * control (residuals and inner/outer decision).
  * The step:outer multiplier update has no kernel of its own in an iteration: the
  * kernels that own the rows apply it in the next iteration, and a call that ends
  * with it pending applies it before returning. */
-#define UCAC_N_KERNELS 7
+#define UCAC_N_KERNELS 5
 
 /* Profiling: run n_iters inner iterations (exactly as ucac_step, same results)
  * with every kernel launched on its own and a HIP event recorded on the handle's

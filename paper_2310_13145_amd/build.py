@@ -1,9 +1,11 @@
 """Build libucac.so (the HIP library behind include/ucac.h) for gfx950, in-tree.
 
-Every kernel file is its own translation unit.  The Newton kernel lets hipcc
-contract a*b+c into FMA; the other kernels are compiled without contraction so
-that their few flops round exactly like plain IEEE FP64 code.  Packed FP32
-instructions are disabled for all device code.
+Every kernel file is its own translation unit.  The Newton kernel's file lets
+hipcc contract a*b+c into FMA (-ffp-contract=fast-honor-pragmas: functions that
+declare contraction off inside it -- the unit side it shares a launch with, the
+bus QP's per-end sums -- keep plain IEEE rounding); the other kernels are compiled
+without contraction so that their few flops round exactly like plain IEEE FP64
+code.  Packed FP32 instructions are disabled for all device code.
 """
 from __future__ import annotations
 
@@ -20,9 +22,8 @@ ARCH = "gfx950"
 
 SOURCES = {
     "ucac_api.hip": "off",
-    "k_uc_dp.hip": "off",
-    "k_gen.hip": "off",
-    "k_branch.hip": "fast",
+    "k_units.hip": "off",
+    "k_branch.hip": "fast-honor-pragmas",
     "k_bar.hip": "off",
     "k_ctl.hip": "off",
     "k_mlp.hip": "off",

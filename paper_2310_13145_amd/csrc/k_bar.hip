@@ -1,13 +1,8 @@
-// step:uc_bar, step:opf_bar and the multiplier updates (step:z, step:y).
+// step:opf_bar and the multiplier updates (step:z, step:y).
 //
-// k_ubar     one lane per (g, t): exact minimiser of the star {ubar_on_t,
-//            ubar_sd_t, ubar_su_{t+1}} in [0,1]^3 (rows U1(t), U3(t), C1..C5(t),
-//            C6(t+1), U2(t+1)); the first period also solves ubar_su_1.  Writes
-//            the new values to a side buffer so that the bus kernel still reads
-//            the previous ones (the Jacobi pair uc_bar || opf_bar).
 // step:opf_bar -- the diagonal QP of every bus-side duplicate subject to the P and Q
 //            balance equations (2x2 KKT system per bus; thetabar a weighted mean,
-//            zero at the reference bus) -- in three coalesced passes:
+//            zero at the reference bus) -- in coalesced passes:
 //            (the line kernel, one lane per (line, t), ends by storing per line end
 //            the four quantities the bus sums need -- P and Q targets, v^2 and angle
 //            centres -- in the bus incidence (CSR) order, so that each bus reads
@@ -15,113 +10,17 @@
 // k_bus      one lane per (bus, t): sums its ends' quantities in incidence order,
 //            solves the KKT system, writes wbar, thetabar and the two balance
 //            multipliers, and updates its generators' duplicates and rows G1, G2;
-// k_bus_post one lane per (line, t): Pbar, Qbar of both ends from the end buses'
-//            multipliers, and z, y of the line's eight rows.
-// The arithmetic is the one-pass gather's, in the same order.
-// k_gen_dual one lane per (g, t): z and y of rows C1..C6 and U1..U3, and commits
-//            the new relaxed commitments.
+//            it reads the previous relaxed commitments (the Jacobi pair
+//            uc_bar || opf_bar: the new ones wait in ub_nxt);
+// k_post     one launch of two block ranges: one lane per (line, t) for Pbar, Qbar
+//            of both ends from the end buses' multipliers and z, y of the line's
+//            eight rows (the arithmetic is the one-pass gather's, in the same
+//            order); then one lane per (g, t) for z and y of rows C1..C6 and
+//            U1..U3, which also commits the new relaxed commitments.
 // Each kernel stores its blocks' residual maxima into per-block slots.
 #include "ucac_launch.hpp"
 
 namespace ucac {
-
-__device__ __forceinline__ void ubar_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
-  if (s.ctl->halt) return;
-  const int G = n.G, T = n.T, TG = T * G;
-  const int i = blk * UBLOCK + threadIdx.x;
-  double dmax = 0.0;
-  if (i < TG) {
-    const int t = i / G, g = i - t * G;
-    const double ruc = p.rho_uc, rc = p.rho_cpl;
-    auto zy = [&](int r, int k, double rho) { return s.zG[r * TG + k] + s.yG[r * TG + k] / rho; };
-    const double h1 = s.uon[i] + zy(RG_U1, i, ruc);
-    const double h3 = s.usd[i] + zy(RG_U3, i, ruc);
-    const double pv = s.p[i], qv = s.q[i];
-    const double hc0 = pv - s.s[0 * TG + i] + zy(RG_C1, i, rc), k0 = n.pmin[g];
-    const double hc1 = pv + s.s[1 * TG + i] + zy(RG_C2, i, rc), k1 = n.pmax[g];
-    const double hc2 = qv - s.s[2 * TG + i] + zy(RG_C3, i, rc), k2 = n.qmin[g];
-    const double hc3 = qv + s.s[3 * TG + i] + zy(RG_C4, i, rc), k3 = n.qmax[g];
-    const double pbp = t == 0 ? n.p0[g] : s.pb[i - G];  // previous duplicate (Jacobi)
-    const double h5 = pv - pbp - s.s[4 * TG + i] + zy(RG_C5, i, rc);
-    const double RD = n.rd[g], SD = n.sd[g], RU = n.ru[g], SU = n.su[g];
-    const bool nxt = t + 1 < T;
-    double h6 = 0.0, h2 = 0.0;
-    if (nxt) {
-      const int kn = i + G;
-      h6 = s.p[kn] - s.pb[i] + s.s[5 * TG + kn] + zy(RG_C6, kn, rc);
-      h2 = s.usu[kn] + zy(RG_U2, kn, ruc);
-    }
-    // b*(a) = clamp(pb + qb a), c*(a) = clamp(pc + qc a)
-    const double den_b = ruc + rc * SD * SD;
-    const double pbv = (ruc * h3 - rc * SD * h5) / den_b, qbv = -(rc * SD * RD) / den_b;
-    const double den_c = ruc + rc * SU * SU;
-    const double pcv = nxt ? (ruc * h2 + rc * SU * h6) / den_c : 0.0;
-    const double qcv = nxt ? -(rc * SU * RU) / den_c : 0.0;
-    // phi'(a) = al a + ga + wb b*(a) + wc c*(a)
-    const double al = ruc + rc * (k0 * k0 + k1 * k1 + k2 * k2 + k3 * k3) + rc * RD * RD + (nxt ? rc * RU * RU : 0.0);
-    const double ga = -ruc * h1 - rc * (k0 * hc0 + k1 * hc1 + k2 * hc2 + k3 * hc3) + rc * RD * h5 - (nxt ? rc * RU * h6 : 0.0);
-    const double wb = rc * RD * SD, wc = nxt ? rc * RU * SU : 0.0;
-    auto dphi = [&](double a) {
-      return al * a + ga + wb * clampd(pbv + qbv * a, 0.0, 1.0) + wc * clampd(pcv + qcv * a, 0.0, 1.0);
-    };
-    double a;
-    if (dphi(0.0) >= 0.0) {
-      a = 0.0;
-    } else if (dphi(1.0) <= 0.0) {
-      a = 1.0;
-    } else {
-      double lo = 0.0, hi = 1.0;
-      double kink[4] = {-1.0, -1.0, -1.0, -1.0};
-      if (qbv != 0.0) { kink[0] = -pbv / qbv; kink[1] = (1.0 - pbv) / qbv; }
-      if (qcv != 0.0) { kink[2] = -pcv / qcv; kink[3] = (1.0 - pcv) / qcv; }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double k = kink[r];
-        if (k > lo && k < hi) {
-          if (dphi(k) < 0.0) lo = k; else hi = k;
-        }
-      }
-      const double m = 0.5 * (lo + hi);
-      const double bm = pbv + qbv * m, cm = pcv + qcv * m;
-      const double B0 = bm <= 0.0 ? 0.0 : (bm >= 1.0 ? 1.0 : pbv), B1 = (bm <= 0.0 || bm >= 1.0) ? 0.0 : qbv;
-      const double C0 = cm <= 0.0 ? 0.0 : (cm >= 1.0 ? 1.0 : pcv), C1 = (cm <= 0.0 || cm >= 1.0) ? 0.0 : qcv;
-      a = clampd(-(ga + wb * B0 + wc * C0) / (al + wb * B1 + wc * C1), lo, hi);
-    }
-    const double b = clampd(pbv + qbv * a, 0.0, 1.0);
-    const int TG3 = TG;
-    double* nx_on = s.ub_nxt;
-    double* nx_su = s.ub_nxt + TG3;
-    double* nx_sd = s.ub_nxt + 2 * TG3;
-    nx_on[i] = a;
-    nx_sd[i] = b;
-    dmax = fmax(fabs(a - s.ubon[i]), fabs(b - s.ubsd[i]));
-    if (nxt) {
-      const double c = clampd(pcv + qcv * a, 0.0, 1.0);
-      nx_su[i + G] = c;
-      dmax = nmax(dmax, fabs(c - s.ubsu[i + G]));
-    }
-    if (t == 0) {
-      // ubar_su at the first period: rows U2(1), C6(1) with ubar_on_0 = u0
-      const double h6f = pv - n.p0[g] + s.s[5 * TG + i] + zy(RG_C6, i, rc);
-      const double h2f = s.usu[i] + zy(RG_U2, i, ruc);
-      const double c0 = clampd((ruc * h2f + rc * SU * (h6f - RU * (double)n.u0[g])) / (ruc + rc * SU * SU), 0.0, 1.0);
-      nx_su[i] = c0;
-      dmax = nmax(dmax, fabs(c0 - s.ubsu[i]));
-    }
-  }
-  const double v[1] = {dmax};
-  const int which[1] = {ACC_RD};
-  block_max_store<1>(v, which, s.red + (size_t)(s.red_ubar + blk) * NACC);
-}
-
-__global__ void __launch_bounds__(UBLOCK) k_ubar(Net n, State s, Par p) { ubar_body(n, s, p, blockIdx.x, gridDim.x); }
-
-__global__ void __launch_bounds__(UBLOCK) k_ubar_group(Group gr) {
-  const int mk = gr.blk_member[blockIdx.x];
-  const Member& M = gr.m[mk];
-  const int b0 = gr.blk_first[mk];
-  ubar_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
-}
 
 // A step:outer multiplier update decided by the previous iteration's control is
 // applied here, by the kernel that owns the row, just before the row's z update
@@ -379,13 +278,9 @@ __global__ void __launch_bounds__(BLOCK) k_post_group(Group gr) {
   post_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-int ubar_blocks(const Net& n) { return (n.T * n.G + UBLOCK - 1) / UBLOCK; }
 int bus_blocks(const Net& n) { return (n.T * n.N + BLOCK - 1) / BLOCK; }
 int post_blocks(const Net& n) { return line_blocks(n) + gen_dual_blocks(n); }
 
-void launch_ubar_grouped(const Group& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_ubar_group, dim3(grid), dim3(UBLOCK), 0, st, g);
-}
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_bus_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
@@ -393,11 +288,6 @@ void launch_post_grouped(const Group& g, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_post_group, dim3(grid), dim3(BLOCK), 0, st, g);
 }
 
-void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st) {
-  const int TG = n.T * n.G;
-  if (TG == 0) return;
-  hipLaunchKernelGGL(k_ubar, dim3(ubar_blocks(n)), dim3(UBLOCK), 0, st, n, s, p);
-}
 
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;

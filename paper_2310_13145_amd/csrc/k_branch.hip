@@ -22,6 +22,7 @@
 #include <hip/hip_ext.h>
 #include "ucac_launch.hpp"
 #include "ucac_mlp.hpp"
+#include "ucac_units.hpp"
 
 namespace ucac {
 
@@ -494,11 +495,31 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_
   branch_body<START, BS>(n, s, p, blockIdx.x);
 }
 
+// The unit side (ucac_units.hpp) and the lines in one launch: blocks [0, nb_units) run
+// the unit side, the rest the line kernel.  Neither reads what the other writes in
+// the same iteration, and one launch on one stream avoids the fork and join that two
+// concurrent launches cost on the iteration's critical path.  The unit blocks come
+// first, so that they start with the first wave of line blocks.
 template <int START, int BS>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_branch_group(Group gr) {
-  const int mk = gr.blk_member[blockIdx.x];
-  const Member& M = gr.m[mk];
-  branch_body<START, BS>(M.n, M.s, M.p, blockIdx.x - gr.blk_first[mk]);
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
+k_front(Net n, State s, Par p, int nb_units, int gpb) {
+  if ((int)blockIdx.x < nb_units) unit_body<BS>(n, s, p, blockIdx.x, n.T, gpb);
+  else branch_body<START, BS>(n, s, p, blockIdx.x - nb_units);
+}
+
+template <int START, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
+k_front_group(Group gu, Group gb, int grid_u, int slotT, int gpb) {
+  const int b = blockIdx.x;
+  if (b < grid_u) {
+    const int mk = gu.blk_member[b];
+    const Member& M = gu.m[mk];
+    unit_body<BS>(M.n, M.s, M.p, b - gu.blk_first[mk], slotT, gpb);
+  } else {
+    const int mk = gb.blk_member[b - grid_u];
+    const Member& M = gb.m[mk];
+    branch_body<START, BS>(M.n, M.s, M.p, b - grid_u - gb.blk_first[mk]);
+  }
 }
 
 // Learned start, run just before the line kernel: every wavefront evaluates the
@@ -531,19 +552,13 @@ int branch_blocks(const Net& n, int block) { return (n.T * n.L + block - 1) / bl
 // dispatch's begin and end timestamps: the kernel's duration without the latency
 // of separate event records around it.
 template <int BS>
-static void launch_branch_bs(const Net* n, const State* s, const Par& p, const Group* g, int grid, int start, hipStream_t st,
+static void launch_branch_bs(const Net& n, const State& s, const Par& p, int grid, int start, hipStream_t st,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (g) {
-    if (start == START_LEARNED) hipLaunchKernelGGL((k_branch_group<START_LEARNED, BS>), dim3(grid), dim3(BS), 0, st, *g);
-    else if (start == START_PREV) hipLaunchKernelGGL((k_branch_group<START_PREV, BS>), dim3(grid), dim3(BS), 0, st, *g);
-    else hipLaunchKernelGGL((k_branch_group<START_FLAT, BS>), dim3(grid), dim3(BS), 0, st, *g);
-    return;
-  }
   void (*kern)(Net, State, Par) = start == START_LEARNED ? k_branch<START_LEARNED, BS>
                                   : start == START_PREV  ? k_branch<START_PREV, BS>
                                                          : k_branch<START_FLAT, BS>;
-  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, e0, e1, 0u, *n, *s, p);
-  else hipLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, *n, *s, p);
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, e0, e1, 0u, n, s, p);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(BS), 0, st, n, s, p);
 }
 
 static void launch_branch_impl(const Net& n, const State& s, const Par& p, hipStream_t st, int block, hipEvent_t e0,
@@ -554,8 +569,8 @@ static void launch_branch_impl(const Net& n, const State& s, const Par& p, hipSt
     hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
   }
   const int grid = branch_blocks(n, block);
-  if (block == 64) launch_branch_bs<64>(&n, &s, p, nullptr, grid, p.warm_start, st, e0, e1);
-  else launch_branch_bs<256>(&n, &s, p, nullptr, grid, p.warm_start, st, e0, e1);
+  if (block == 64) launch_branch_bs<64>(n, s, p, grid, p.warm_start, st, e0, e1);
+  else launch_branch_bs<256>(n, s, p, grid, p.warm_start, st, e0, e1);
 }
 
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block) {
@@ -568,10 +583,38 @@ void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t
 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_branch_block(n, s, p, st, 256); }
 
-void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st) {
-  const Par dummy{};
-  if (block == 64) launch_branch_bs<64>(nullptr, nullptr, dummy, &g, grid, warm_start, st);
-  else launch_branch_bs<256>(nullptr, nullptr, dummy, &g, grid, warm_start, st);
+void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const int TL = n.T * n.L;
+  const int gpb = units_gpb(n.T, 16, 256);
+  const int nu = n.G && n.T ? units_blocks(n, gpb) : 0;
+  const int nb = TL ? branch_blocks(n, 256) : 0;
+  if (nu + nb == 0) return;
+  if (TL && p.warm_start == START_LEARNED) {
+    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
+    hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
+  }
+  const size_t lds = nu ? units_lds(n.T, gpb) : 0;
+  const dim3 grid(nu + nb), block(256);
+  if (p.warm_start == START_LEARNED) hipLaunchKernelGGL((k_front<START_LEARNED, 256>), grid, block, lds, st, n, s, p, nu, gpb);
+  else if (p.warm_start == START_PREV) hipLaunchKernelGGL((k_front<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb);
+  else hipLaunchKernelGGL((k_front<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb);
+}
+
+template <int BS>
+static void launch_front_bs(const Group& gu, int grid_u, const Group& gb, int grid_b, int warm_start, int gpb, int max_T,
+                            hipStream_t st) {
+  const size_t lds = grid_u ? units_lds(max_T, gpb) : 0;
+  const dim3 grid(grid_u + grid_b), block(BS);
+  if (warm_start == START_PREV) hipLaunchKernelGGL((k_front_group<START_PREV, BS>), grid, block, lds, st, gu, gb, grid_u, max_T, gpb);
+  else hipLaunchKernelGGL((k_front_group<START_FLAT, BS>), grid, block, lds, st, gu, gb, grid_u, max_T, gpb);
+}
+
+void launch_front_grouped(const Group& gu, int grid_u, const Group& gb, int grid_b, int warm_start, int block,
+                          int dp_lanes, int max_T, hipStream_t st) {
+  if (grid_u + grid_b == 0) return;
+  const int gpb = units_gpb(max_T, dp_lanes, block == 64 ? 64 : 256);
+  if (block == 64) launch_front_bs<64>(gu, grid_u, gb, grid_b, warm_start, gpb, max_T, st);
+  else launch_front_bs<256>(gu, grid_u, gb, grid_b, warm_start, gpb, max_T, st);
 }
 
 }  // namespace ucac

@@ -54,8 +54,6 @@ struct ucac_handle {
   hipGraphExec_t exec = nullptr;    // one iteration
   hipGraphExec_t exec_u = nullptr;  // GRAPH_UNROLL iterations back to back
   hipEvent_t ev_poll = nullptr;
-  hipStream_t side = nullptr;        // second capture stream of the iteration graph
-  hipEvent_t ev[2] = {};             // capture-time fork/join events of the graph
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
@@ -195,8 +193,8 @@ size_t carve(ucac_handle* h, char* base) {
   s.br_iters = a.take<int>(T * L);
   s.x0 = a.take<float>(4 * T * L);
   s.br_count = a.take<unsigned long long>(branch_waves(h) * 5);
-  s.red_ubar = 0;
-  s.red_bus = s.red_ubar + ubar_blocks(n);
+  s.red_units = 0;
+  s.red_bus = s.red_units + n.G;  // one slot per unit block: at most one block per generator
   s.red_bpost = s.red_bus + bus_blocks(n);
   s.red_gdual = s.red_bpost + line_blocks(n);
   s.red_n = s.red_gdual + gen_dual_blocks(n);
@@ -427,59 +425,51 @@ Par kernel_params(const ucac_params& p) {
   return k;
 }
 
-// Enqueue one inner iteration for capture.  step:uc and the generator part of
-// step:opf do not depend on the line kernel, and step:uc_bar depends only on them
-// (it reads the previous pbar, which the bus kernel then overwrites), so these three
-// run on a side stream beside the line kernel.  After the bus QP, one launch
-// finishes the line ends and updates the coupling/commitment multipliers:
+// Enqueue one inner iteration for capture, on one stream:
 //
-//   main: branch ----------+-> bus -> post -> finalize
-//   side: uc_dp -> gen -> ubar
+//   front (unit side | lines) -> bus -> post -> finalize
 //
-// launch(k, stream) launches kernel k (K_* order) and returns hipGetLastError();
-// ev[0..1]: capture-time fork/join events.
+// The unit side (generator update, step:uc, step:uc_bar; per generator) does not
+// depend on the line kernel and vice versa, so both run in one launch of two block
+// ranges; step:uc_bar reads the previous pbar, which the bus kernel then overwrites.
+// After the bus QP, one launch finishes the line ends and updates the
+// coupling/commitment multipliers.  Consecutive launches on one stream start back
+// to back; a fork/join between two streams cost several microseconds per iteration.
+//
+// launch(k, stream) launches kernel k (K_FRONT or a K_* index) and returns
+// hipGetLastError().
 template <class F>
-hipError_t enqueue_forked(F launch, hipStream_t main, hipStream_t side, hipEvent_t* ev, const char** where) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "post", "finalize"};
-  hipError_t e = hipSuccess;
-  auto run = [&](int k, hipStream_t s) {
-    if (e == hipSuccess) {
-      e = launch(k, s);
-      if (e != hipSuccess && where) *where = names[k];
+hipError_t enqueue_chain(F launch, hipStream_t st, const char** where) {
+  static const char* names[] = {"front", "bus", "post", "finalize"};
+  const int ks[] = {K_FRONT, K_BUS, K_POST, K_FINALIZE};
+  for (int i = 0; i < 4; ++i) {
+    const hipError_t e = launch(ks[i], st);
+    if (e != hipSuccess) {
+      if (where) *where = names[i];
+      return e;
     }
-  };
-  auto link = [&](hipStream_t from, hipStream_t to, hipEvent_t evt) {
-    if (e == hipSuccess) e = hipEventRecord(evt, from);
-    if (e == hipSuccess) e = hipStreamWaitEvent(to, evt, 0);
-    if (e != hipSuccess && where && !*where) *where = "fork/join";
-  };
-  link(main, side, ev[0]);
-  run(K_BRANCH, main);  // captured first: the longest kernel is dispatched first
-  run(K_UC_DP, side);
-  run(K_GEN, side);
-  run(K_UBAR, side);
-  link(side, main, ev[1]);
-  run(K_BUS, main);
-  run(K_POST, main);
-  run(K_FINALIZE, main);
-  return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where) {
-  static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_post, launch_finalize};
   auto launch = [&](int k, hipStream_t s) {
-    fns[k](h->net, h->st, h->kp, s);
+    switch (k) {
+      case K_FRONT: launch_front(h->net, h->st, h->kp, s); break;
+      case K_BUS: launch_bus(h->net, h->st, h->kp, s); break;
+      case K_POST: launch_post(h->net, h->st, h->kp, s); break;
+      default: launch_finalize(h->net, h->st, h->kp, s); break;
+    }
     return hipGetLastError();
   };
-  return enqueue_forked(launch, st, h->side, h->ev, where);
+  return enqueue_chain(launch, st, where);
 }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
-  static const char* names[] = {"uc_dp", "gen", "branch", "ubar", "bus", "post", "finalize"};
+  static const char* names[] = {"units", "branch", "bus", "post", "finalize"};
   static void (*const fns[])(const Net&, const State&, const Par&, hipStream_t) = {
-      launch_uc_dp, launch_gen, launch_branch, launch_ubar, launch_bus, launch_post, launch_finalize};
+      launch_units, launch_branch, launch_bus, launch_post, launch_finalize};
   fns[k](h->net, sv ? *sv : h->st, h->kp, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess && where) *where = names[k];
@@ -635,9 +625,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
       hipHostMalloc((void**)&h->h_sc, sizeof(double) * NSC, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(h, UCAC_E_NOMEM, "pinned host allocation failed"));
   bool ev_ok = hipEventCreateWithFlags(&h->ev_poll, hipEventDisableTiming) == hipSuccess;
-  for (hipEvent_t& e : h->ev) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   if (!ev_ok) return cleanup(fail(h, UCAC_E_DEVICE, "event create failed"));
-  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(h, UCAC_E_DEVICE, "stream create failed"));
 
   const Net& n = h->net;
   struct Up { void* dst; const void* src; size_t bytes; } ups[] = {
@@ -1262,9 +1250,6 @@ void ucac_destroy(ucac_handle* h) {
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->graph_u) (void)hipGraphDestroy(h->graph_u);
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
-  for (hipEvent_t e : h->ev)
-    if (e) (void)hipEventDestroy(e);
-  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_sc) (void)hipHostFree(h->h_sc);
@@ -1281,8 +1266,7 @@ struct ucac_batch {
   int device = 0;
   int warm_start = 0;
   std::vector<ucac_handle*> m;
-  hipStream_t st = nullptr, side = nullptr;
-  hipEvent_t ev[2] = {};
+  hipStream_t st = nullptr;
   Member* d_members = nullptr;
   int* d_tables = nullptr;       // per kernel: blk_member [grid], blk_first [n], blk_count [n]
   Group grp[K_COUNT]{};
@@ -1313,12 +1297,10 @@ int bfail(ucac_batch* b, int code, const char* fmt, ...) {
     if (_e != hipSuccess) return bfail(b, UCAC_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
   } while (0)
 
-int kernel_blocks(int k, const Net& n, const ucac_batch_config& c) {
+int kernel_blocks(int k, const Net& n, const ucac_batch_config& c, int max_T) {
   switch (k) {
-    case K_UC_DP: return n.G ? uc_dp_blocks(n, c.dp_lanes) : 0;
-    case K_GEN: return gen_blocks(n);
+    case K_UNITS: return n.G && n.T ? units_blocks(n, units_gpb(max_T, c.dp_lanes, c.branch_block == 64 ? 64 : 256)) : 0;
     case K_BRANCH: return branch_blocks(n, c.branch_block);
-    case K_UBAR: return ubar_blocks(n);
     case K_BUS: return bus_blocks(n);
     case K_POST: return post_blocks(n);
     case K_FINALIZE: return 1;
@@ -1340,7 +1322,7 @@ int batch_build(ucac_batch* b) {
   for (int k = 0; k < K_COUNT; ++k) {
     std::vector<int> first(n, 0), count(n, 0), member;
     for (int j : order) {
-      const int nb = kernel_blocks(k, b->m[j]->net, b->cfg);
+      const int nb = kernel_blocks(k, b->m[j]->net, b->cfg, b->max_T);
       first[j] = (int)member.size();
       count[j] = nb;
       for (int q = 0; q < nb; ++q) member.push_back(j);
@@ -1367,13 +1349,14 @@ int batch_build(ucac_batch* b) {
   if (b->graph_u) { (void)hipGraphDestroy(b->graph_u); b->graph_u = nullptr; }
   const char* where = "";
   auto launch = [&](int k, hipStream_t s) {
+    if (k == K_FRONT) {
+      launch_front_grouped(b->grp[K_UNITS], b->grid[K_UNITS], b->grp[K_BRANCH], b->grid[K_BRANCH], b->warm_start,
+                           b->cfg.branch_block, b->cfg.dp_lanes, b->max_T, s);
+      return hipGetLastError();
+    }
     if (b->grid[k] == 0) return hipSuccess;
     const Group& g = b->grp[k];
     switch (k) {
-      case K_UC_DP: launch_uc_dp_grouped(g, b->grid[k], b->cfg.dp_lanes, b->max_T, s); break;
-      case K_GEN: launch_gen_grouped(g, b->grid[k], s); break;
-      case K_BRANCH: launch_branch_grouped(g, b->grid[k], b->warm_start, b->cfg.branch_block, s); break;
-      case K_UBAR: launch_ubar_grouped(g, b->grid[k], s); break;
       case K_BUS: launch_bus_grouped(g, b->grid[k], s); break;
       case K_POST: launch_post_grouped(g, b->grid[k], s); break;
       case K_FINALIZE: launch_finalize_grouped(g, b->grid[k], s); break;
@@ -1385,7 +1368,7 @@ int batch_build(ucac_batch* b) {
     (void)hipGetLastError();
     BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
-    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_forked(launch, b->st, b->side, b->ev, &where);
+    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_chain(launch, b->st, &where);
     hipGraph_t& gr = reps == 1 ? b->graph : b->graph_u;
     const hipError_t ce = hipStreamEndCapture(b->st, &gr);
     if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
@@ -1471,11 +1454,8 @@ int ucac_batch_create(const ucac_network* nets, int32_t n, const ucac_params* pa
     b->max_T = std::max(b->max_T, h->T);
   }
   if (hipSetDevice(b->device) != hipSuccess) return bad(bfail(nullptr, UCAC_E_DEVICE, "hipSetDevice failed"));
-  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess)
-    return bad(bfail(nullptr, UCAC_E_DEVICE, "stream/event create failed"));
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess)
+    return bad(bfail(nullptr, UCAC_E_DEVICE, "stream create failed"));
   std::vector<Member> hm(n);
   for (int k = 0; k < n; ++k) hm[k] = Member{b->m[k]->net, b->m[k]->st, b->m[k]->kp};
   if (hipMalloc(&b->d_members, sizeof(Member) * n) != hipSuccess ||
@@ -1654,9 +1634,6 @@ void ucac_batch_destroy(ucac_batch* b) {
   if (b->graph_u) (void)hipGraphDestroy(b->graph_u);
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_members) (void)hipFree(b->d_members);
-  for (hipEvent_t e : b->ev)
-    if (e) (void)hipEventDestroy(e);
-  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->st) (void)hipStreamDestroy(b->st);
   for (ucac_handle* h : b->m) ucac_destroy(h);
   delete b;

@@ -78,8 +78,8 @@ struct State {
   int* br_iters;                                               // [T][L]
   unsigned long long* br_count;  // [waves][5] running totals per wavefront of the line kernel (global lane / 64):
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks
-  double* red;                   // [red_n][NACC] per-block residual maxima of ubar, bus and post (line ends, then generator rows)
-  int red_ubar, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
+  double* red;                   // [red_n][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
+  int red_units, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
   double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres
   double* bmu;                   // [2][T][N] balance multipliers of the bus QP
   float* x0;                     // [4][T][L] start points of the learned Newton start (FP32)

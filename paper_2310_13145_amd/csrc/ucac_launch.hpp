@@ -3,14 +3,13 @@
 #include "ucac_dev.hpp"
 
 namespace ucac {
-void launch_uc_dp(const Net& n, const State& s, const Par& p, hipStream_t st);
-void launch_uc_dp_lanes(const Net& n, const State& s, const Par& p, hipStream_t st, int dp_lanes);
-void launch_gen(const Net& n, const State& s, const Par& p, hipStream_t st);
+// the unit side (generator update, UC dynamic program, relaxed commitments) per generator
+void launch_units(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_units_lanes(const Net& n, const State& s, const Par& p, hipStream_t st, int dp_lanes);
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block);
 // The line kernel at 256-lane blocks, timed by the dispatch's own start/stop events.
 void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
-void launch_ubar(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);
@@ -24,24 +23,26 @@ struct Tuning {
   int branch_block = 256;
 };
 // K_ITER kernels per iteration; K_LAMBDA flushes a pending multiplier update after a call
-enum { K_UC_DP, K_GEN, K_BRANCH, K_UBAR, K_BUS, K_POST, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT };
-int uc_dp_blocks(const Net& n, int dp_lanes);
-int gen_blocks(const Net& n);
+// K_FRONT: the unit side and the lines in one launch (the units' and the lines' block
+// tables side by side); the iteration graph runs K_FRONT, K_BUS, K_POST, K_FINALIZE.
+enum { K_UNITS, K_BRANCH, K_BUS, K_POST, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT, K_FRONT = K_COUNT };
+int units_gpb(int T, int dp_lanes, int bs);  // generators per unit block of bs threads
+size_t units_lds(int T, int gpb);    // dynamic LDS of a unit block
+int units_blocks(const Net& n, int gpb);
 int branch_blocks(const Net& n, int block);
-int ubar_blocks(const Net& n);
 int bus_blocks(const Net& n);
 int post_blocks(const Net& n);
 int lambda_blocks(const Net& n);
-void launch_uc_dp_grouped(const Group& g, int grid, int dp_lanes, int max_T, hipStream_t st);
-void launch_gen_grouped(const Group& g, int grid, hipStream_t st);
-void launch_branch_grouped(const Group& g, int grid, int warm_start, int block, hipStream_t st);
-void launch_ubar_grouped(const Group& g, int grid, hipStream_t st);
+// the unit side and the lines in one launch: the units' blocks first, then the lines'
+void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_front_grouped(const Group& gu, int grid_u, const Group& gb, int grid_b, int warm_start, int block,
+                          int dp_lanes, int max_T, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);
 void launch_post_grouped(const Group& g, int grid, hipStream_t st);
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st);
 void launch_lambda_grouped(const Group& g, int grid, hipStream_t st);
 
-// standalone UC dynamic programs on given tables (k_uc_dp.hip)
+// standalone UC dynamic programs on given tables (k_units.hip)
 size_t dp_tables_lds(int T, int lanes);
 void launch_dp_tables(const double* tab, int G, int T, const int* tu, const int* td, const int* u0, const int* lon,
                       const int* loff, signed char* u_out, double* cost_out, int lanes, hipStream_t st);

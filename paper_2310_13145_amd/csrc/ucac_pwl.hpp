@@ -6,6 +6,7 @@
 // D(a) < 0 <= D(b) is shrunk at every kink inside it -- no sorting, no dynamically
 // indexed arrays, so everything stays in registers -- and the root is the zero of
 // the one linear piece left, whose active rows are read at the bracket midpoint.
+// Plain IEEE arithmetic (contraction off) in any translation unit.
 #pragma once
 #include "ucac_dev.hpp"
 
@@ -18,6 +19,7 @@ struct Pwl {
   bool neg[NR];
 
   __device__ inline double D(double x) const {
+#pragma clang fp contract(off)
     double d = A * x + B;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -28,6 +30,7 @@ struct Pwl {
   }
 
   __device__ inline double argmin(double lo, double hi) const {
+#pragma clang fp contract(off)
     if (D(lo) >= 0.0) return lo;
     if (D(hi) <= 0.0) return hi;
     double a = lo, b = hi;

@@ -267,7 +267,7 @@ def ucac_get_branch_iters(h, n_line, T):
     return out
 
 
-KERNELS = ("uc_dp", "gen", "branch", "ubar", "bus", "post", "finalize")
+KERNELS = ("units", "branch", "bus", "post", "finalize")
 
 
 def ucac_kernel_times(h, n_iters):
