@@ -27,7 +27,17 @@ constexpr int FIN_BLOCK = 256;  // largest block that runs the control step
 // residual slot of the iteration, advance the counters and decide (see above).
 __device__ inline void finalize_body(const State& s, const Par& p) {
   Ctl* c = s.ctl;
-  if (c->halt) return;
+  double* sc = s.sc;
+  // The control fields and counters are loaded first (uniform addresses), so that
+  // their latency overlaps the slot loads; a halted instance is checked only
+  // before the stores (the reduction itself only reads).
+  const int halt = c->halt, stop = c->stop_at_tol, ms_count = c->ms_count;
+  const double tol = c->tol;
+  int ms_iter[3];
+  double ms_tol[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { ms_iter[k] = c->ms_iter[k]; ms_tol[k] = c->ms_tol[k]; }
+  const double it = sc[SC_ITER], lin = sc[SC_LIN], kout = sc[SC_KOUT], beta = sc[SC_BETA], zprev = sc[SC_ZPREV];
   // reduce the per-block maxima of this iteration's kernels
   // up to 8 slots per thread per round, all loads issued before the first use
   double m[NACC] = {0.0, 0.0, 0.0, 0.0};
@@ -53,39 +63,39 @@ __device__ inline void finalize_body(const State& s, const Par& p) {
     for (int k = 0; k < NACC; ++k) part[k][threadIdx.x >> 6] = m[k];
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || halt) return;
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m[k] = nmax(m[k], part[k][w]);
     m[k] = nmax(m[k], part[k][0]);
   }
-  double* sc = s.sc;
   const double rp = m[ACC_RP], rin = m[ACC_RIN], rd = m[ACC_RD], zinf = m[ACC_ZINF];
   sc[SC_RP] = rp;
   sc[SC_RIN] = rin;
   sc[SC_RD] = rd;
   sc[SC_ZINF] = zinf;
-  sc[SC_ITER] += 1.0;
-  sc[SC_LIN] += 1.0;
+  sc[SC_ITER] = it + 1.0;
   c->pending = 0;
   if (rp != rp || rin != rin || rd != rd || zinf != zinf) c->bad = 1;
-  c->ms_count += 1;
-  for (int m = 0; m < 3; ++m)
-    if (c->ms_iter[m] < 0 && rp <= c->ms_tol[m] && rd <= c->ms_tol[m]) c->ms_iter[m] = c->ms_count;
-  if (c->stop_at_tol && rp <= c->tol && rd <= c->tol) {
+  c->ms_count = ms_count + 1;
+  for (int k = 0; k < 3; ++k)
+    if (ms_iter[k] < 0 && rp <= ms_tol[k] && rd <= ms_tol[k]) c->ms_iter[k] = ms_count + 1;
+  if (stop && rp <= tol && rd <= tol) {
+    sc[SC_LIN] = lin + 1.0;
     sc[SC_CONV] = 1.0;
     c->halt = 1;
     return;
   }
-  const double eps = fmax(0.5 * c->tol, p.eps_in0 * ldexp(1.0, -(int)sc[SC_KOUT]));
-  if (fmax(rin, rd) <= eps || sc[SC_LIN] >= (double)p.max_inner) {
-    const double beta = sc[SC_BETA];
+  const double eps = fmax(0.5 * tol, p.eps_in0 * ldexp(1.0, -(int)kout));
+  if (fmax(rin, rd) <= eps || lin + 1.0 >= (double)p.max_inner) {
     c->pending = 1;
     c->beta_for_lambda = beta;
-    if (zinf > p.theta * sc[SC_ZPREV]) sc[SC_BETA] = fmin(p.tau * beta, p.beta_max);
+    if (zinf > p.theta * zprev) sc[SC_BETA] = fmin(p.tau * beta, p.beta_max);
     sc[SC_ZPREV] = zinf;
-    sc[SC_KOUT] += 1.0;
+    sc[SC_KOUT] = kout + 1.0;
     sc[SC_LIN] = 0.0;
+  } else {
+    sc[SC_LIN] = lin + 1.0;
   }
 }
 
