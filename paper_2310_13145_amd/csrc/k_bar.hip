@@ -53,6 +53,34 @@ __device__ inline void zy_update(double* zr, double* yr, double* lr, int k, doub
   zinf = nmax(zinf, fabs(z));
 }
 
+// The same update split into load, update and store, so that a lane issues the
+// loads of all its rows before its first store (a store may alias any later load,
+// so interleaving them costs one memory round trip per row).
+struct RowZY {
+  double z, y, l;
+};
+
+__device__ inline RowZY row_load(const double* zr, const double* yr, const double* lr, int k) {
+  return RowZY{zr[k], yr[k], lr[k]};
+}
+
+__device__ inline void row_update(RowZY& r, double a, double rho, double beta, const LamUpd& lu, double& rp, double& rin,
+                                  double& zinf) {
+  if (lu.on) r.l = clampd(r.l + lu.b * r.z, -lu.lm, lu.lm);
+  const double z = -(r.l + r.y + rho * a) / (beta + rho);
+  r.y = r.y + rho * (a + z);
+  r.z = z;
+  rp = nmax(rp, fabs(a));
+  rin = nmax(rin, fabs(a + z));
+  zinf = nmax(zinf, fabs(z));
+}
+
+__device__ inline void row_store(const RowZY& r, double* zr, double* yr, double* lr, int k, const LamUpd& lu) {
+  zr[k] = r.z;
+  yr[k] = r.y;
+  if (lu.on) lr[k] = r.l;
+}
+
 
 
 struct EndData {
@@ -184,23 +212,38 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
     const double rpq = p.rho_pq, rva = p.rho_va;
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
+    // every load of both ends first, then the updates, then the stores
+    EndData d[2];
+    double mu1[2], mu2[2], wnew[2], thnew[2], Pold[2], Qold[2];
+    RowZY r[2][4];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int code = 2 * l + side;
-      const EndData d = load_end(n, s, t, TL, code, rpq);
+      d[side] = load_end(n, s, t, TL, 2 * l + side, rpq);
       const int b = t * n.N + (side ? n.to[l] : n.from[l]);
-      const double mu1 = s.bmu[b], mu2 = s.bmu[TN + b], wnew = s.wb[b], thnew = s.thb[b];
+      mu1[side] = s.bmu[b]; mu2[side] = s.bmu[TN + b]; wnew[side] = s.wb[b]; thnew[side] = s.thb[b];
+      const int k = d[side].k;
+      Pold[side] = side ? s.Pbt[k] : s.Pbf[k];
+      Qold[side] = side ? s.Qbt[k] : s.Qbf[k];
+      const int rows[4] = {d[side].rP, d[side].rQ, d[side].rW, d[side].rT};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[side][q] = row_load(s.zB + rows[q] * TL, s.yB + rows[q] * TL, s.lB + rows[q] * TL, k);
+    }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const EndData& q = d[side];
+      const double Pn = q.tP - mu1[side] / rpq, Qn = q.tQ - mu2[side] / rpq;
+      rd = nmax(rd, nmax(fabs(Pn - Pold[side]), fabs(Qn - Qold[side])));
+      row_update(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf);
+      row_update(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf);
+      row_update(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf);
+      row_update(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf);
       double* Pdup = side ? s.Pbt : s.Pbf;
       double* Qdup = side ? s.Qbt : s.Qbf;
-      const int k = d.k;
-      const double Pn = d.tP - mu1 / rpq, Qn = d.tQ - mu2 / rpq;
-      rd = nmax(rd, nmax(fabs(Pn - Pdup[k]), fabs(Qn - Qdup[k])));
-      Pdup[k] = Pn;
-      Qdup[k] = Qn;
-      zy_update(s.zB + d.rP * TL, s.yB + d.rP * TL, s.lB + d.rP * TL, k, d.fP - Pn, rpq, beta, lu, rp, rin, zinf);
-      zy_update(s.zB + d.rQ * TL, s.yB + d.rQ * TL, s.lB + d.rQ * TL, k, d.fQ - Qn, rpq, beta, lu, rp, rin, zinf);
-      zy_update(s.zB + d.rW * TL, s.yB + d.rW * TL, s.lB + d.rW * TL, k, d.v * d.v - wnew, rva, beta, lu, rp, rin, zinf);
-      zy_update(s.zB + d.rT * TL, s.yB + d.rT * TL, s.lB + d.rT * TL, k, d.th - thnew, rva, beta, lu, rp, rin, zinf);
+      Pdup[q.k] = Pn;
+      Qdup[q.k] = Qn;
+      const int rows[4] = {q.rP, q.rQ, q.rW, q.rT};
+#pragma unroll
+      for (int w = 0; w < 4; ++w) row_store(r[side][w], s.zB + rows[w] * TL, s.yB + rows[w] * TL, s.lB + rows[w] * TL, q.k, lu);
     }
   }
   const double v[4] = {rp, rin, rd, zinf};
@@ -243,12 +286,13 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
     a[6] = s.uon[i] - uon;
     a[7] = s.usu[i] - usu;
     a[8] = s.usd[i] - usd;
+    RowZY rz[9];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int row = RG_C1 + r;
-      const double rho = r < 6 ? p.rho_cpl : p.rho_uc;
-      zy_update(s.zG + row * TG, s.yG + row * TG, s.lG + row * TG, i, a[r], rho, beta, lu, rp, rin, zinf);
-    }
+    for (int r = 0; r < 9; ++r) rz[r] = row_load(s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) row_update(rz[r], a[r], r < 6 ? p.rho_cpl : p.rho_uc, beta, lu, rp, rin, zinf);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) row_store(rz[r], s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i, lu);
     s.ubon[i] = uon;
     s.ubsu[i] = usu;
     s.ubsd[i] = usd;
