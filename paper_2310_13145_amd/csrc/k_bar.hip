@@ -38,24 +38,12 @@ __device__ inline LamUpd lambda_pending(const State& s, const Par& p) {
   return u;
 }
 
-__device__ inline void zy_update(double* zr, double* yr, double* lr, int k, double a, double rho, double beta,
-                                 const LamUpd& lu, double& rp, double& rin, double& zinf) {
-  double lam = lr[k];
-  if (lu.on) {
-    lam = clampd(lam + lu.b * zr[k], -lu.lm, lu.lm);
-    lr[k] = lam;
-  }
-  const double z = -(lam + yr[k] + rho * a) / (beta + rho);
-  zr[k] = z;
-  yr[k] = yr[k] + rho * (a + z);
-  rp = nmax(rp, fabs(a));
-  rin = nmax(rin, fabs(a + z));
-  zinf = nmax(zinf, fabs(z));
-}
-
-// The same update split into load, update and store, so that a lane issues the
-// loads of all its rows before its first store (a store may alias any later load,
-// so interleaving them costs one memory round trip per row).
+// step:z and step:y of one row with value a = (Ax + Bxbar)_r, in three parts so that
+// a lane issues the loads of all its rows before its first store (a store may
+// alias any later load, so interleaving them costs one memory round trip per row):
+//   z <- -(lambda + y + rho a) / (beta + rho),  y <- y + rho (a + z),
+// with a pending step:outer update lambda <- clamp(lambda + beta_prev z_prev) first.
+// The residual maxima r_p = |a|, r_in = |a + z| and ||z|| are accumulated.
 struct RowZY {
   double z, y, l;
 };
@@ -171,10 +159,6 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double mu2 = (M11 * r2 - M12 * r1) / det;
     const double wnew = has_w ? tauw + (aw * mu1 + bw * mu2) / Ww : wold;
     const double thnew = (i == n.ref) ? 0.0 : (Wt > 0.0 ? St / Wt : thold);
-    s.wb[idx] = wnew;
-    s.thb[idx] = thnew;
-    s.bmu[idx] = mu1;
-    s.bmu[T * N + idx] = mu2;
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
     for (int e = g0; e < g1; ++e) {
       const int g = n.gen_list[e], k = t * G + g;
@@ -190,12 +174,21 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
       }
       const double tq = s.q[k] + s.zG[RG_G2 * TG + k] + s.yG[RG_G2 * TG + k] / rpq;
       const double pn = Sp / Wp + mu1 / Wp, qn = tq + mu2 / rpq;
-      rd = nmax(rd, nmax(fabs(pn - s.pb[k]), fabs(qn - s.qb[k])));
+      const double pold = s.pb[k], qold = s.qb[k], pv = s.p[k], qv = s.q[k];
+      RowZY r1 = row_load(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k);
+      RowZY r2 = row_load(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k);
+      rd = nmax(rd, nmax(fabs(pn - pold), fabs(qn - qold)));
+      row_update(r1, pv - pn, rpq, beta, lu, rp, rin, zinf);
+      row_update(r2, qv - qn, rpq, beta, lu, rp, rin, zinf);
       s.pb[k] = pn;
       s.qb[k] = qn;
-      zy_update(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k, s.p[k] - pn, rpq, beta, lu, rp, rin, zinf);
-      zy_update(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k, s.q[k] - qn, rpq, beta, lu, rp, rin, zinf);
+      row_store(r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k, lu);
+      row_store(r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k, lu);
     }
+    s.wb[idx] = wnew;
+    s.thb[idx] = thnew;
+    s.bmu[idx] = mu1;
+    s.bmu[T * N + idx] = mu2;
   }
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};

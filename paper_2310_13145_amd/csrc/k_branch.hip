@@ -432,6 +432,12 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
       it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, conv);
     }
+    // z, y of the eight rows for the per-end sums below, loaded before this lane's
+    // first store so that their latency overlaps the final flows
+    double zz[8], yy[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) { zz[r] = s.zB[r * TL + idx]; yy[r] = s.yB[r * TL + idx]; }
+    const int epos0 = n.end_pos[2 * (idx % n.L)], epos1 = n.end_pos[2 * (idx % n.L) + 1];
     double S, C;
     sincos(x[2] - x[3], &S, &C);
     double f0, f1, f2, f3;
@@ -446,18 +452,19 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
       // angle centres of both ends, stored at each end's place in its bus's incidence
       // list, in plain IEEE arithmetic (no contraction) like the bus solve itself
 #pragma clang fp contract(off)
-      const int t = idx / n.L, l = idx - t * n.L;
+      const int t = idx / n.L;
       double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;
       const double fP[2] = {f0, f2}, fQ[2] = {f1, f3}, v[2] = {x[0], x[1]}, th[2] = {x[2], x[3]};
+      const int epos[2] = {epos0, epos1};
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int rP = side ? RB_PT : RB_PF, rQ = side ? RB_QT : RB_QF;
         const int rW = side ? RB_WT : RB_WF, rT = side ? RB_TT : RB_TF;
-        double* o = eb + (size_t)n.end_pos[2 * l + side] * 4;
-        o[0] = fP[side] + s.zB[rP * TL + idx] + s.yB[rP * TL + idx] / L.rpq;
-        o[1] = fQ[side] + s.zB[rQ * TL + idx] + s.yB[rQ * TL + idx] / L.rpq;
-        o[2] = v[side] * v[side] + s.zB[rW * TL + idx] + s.yB[rW * TL + idx] / L.rva;
-        o[3] = th[side] + s.zB[rT * TL + idx] + s.yB[rT * TL + idx] / L.rva;
+        double* o = eb + (size_t)epos[side] * 4;
+        o[0] = fP[side] + zz[rP] + yy[rP] / L.rpq;
+        o[1] = fQ[side] + zz[rQ] + yy[rQ] / L.rpq;
+        o[2] = v[side] * v[side] + zz[rW] + yy[rW] / L.rva;
+        o[3] = th[side] + zz[rT] + yy[rT] / L.rva;
       }
     }
     if (s.log_feat && idx % s.log_stride == s.log_phase) {
