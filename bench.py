@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 FLOP_EVAL = 349      # value + gradient + 10-entry Hessian at one point (inactive line limits)
 FLOP_TRIAL = 75      # value only at a trial point (what a rejected trial needs)
 FLOP_CG = 80         # one Steihaug-Toint CG iteration on the 4x4 system
+FLOP_DIRECT = 110    # one Newton step by the 4x4 LDL^T factorization (free-set assembly, 4 refined
+                     # reciprocals, elimination, triangular solves, length test)
 FLOP_NEWTON = 80     # per trust-region iteration: projection, predicted reduction, ratio, radius
 FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, final flows, nu update,
                      # the bus QP's per-end sums
@@ -347,7 +349,7 @@ def main():
     # only the value at rejected ones, which is what is counted
     full = cnt["evals"] - cnt["rejected"]
     flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
-                        cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
+                        cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
     br_s = branch_dispatch_ms * 1e-3
     achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN

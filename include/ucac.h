@@ -171,8 +171,10 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
  * solve and one at every trial point; after a rejected trial the gradient and
  * Hessian of the current point are reused, not formed again), out[1]
  * rejected trial steps, out[2] CG iterations, out[3] Newton iterations, out[4]
- * learned starts that fell back to the flat start (out has 5 slots).  reset != 0
- * zeroes them after reading. */
+ * learned starts that fell back to the flat start, out[5] Newton steps taken
+ * from the direct 4x4 factorization instead of CG (the free-subspace Hessian
+ * positive definite and the step inside the trust region, where CG returns the
+ * same step); out has 6 slots.  reset != 0 zeroes them after reading. */
 int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
 
 /* After ucac_solve (or ucac_step): first_iter[m] (m = 0, 1, 2) receives the first

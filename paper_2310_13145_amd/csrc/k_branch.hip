@@ -230,6 +230,46 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
   for (int i = 0; i < 4; ++i) out[i] = z[i];
 }
 
+// The Newton step of the free subspace by a 4x4 LDL^T factorization, when it is what
+// Steihaug-Toint CG returns: if H restricted to the free variables is positive
+// definite, CG's iterates grow monotonically in norm and it ends (in at most nf
+// iterations, in exact arithmetic) at the solution of H_ff s = -g_f; if that
+// solution lies strictly inside the trust region, no iterate reached the boundary
+// and CG returns it.  Returns true with that step in d; false (indefinite H_ff or a
+// step of length >= delta) leaves the step to CG.  The fixed variables get identity
+// rows, so their step is zero.  About 70 operations against about 120 per CG
+// iteration.
+__device__ inline bool newton_step_direct(const Sym4& H, const double (&g)[4], const double (&fr)[4], double delta,
+                                          double (&d)[4]) {
+  const double a00 = fr[0] * H.h00 + (1.0 - fr[0]), a11 = fr[1] * H.h11 + (1.0 - fr[1]);
+  const double a22 = fr[2] * H.h22 + (1.0 - fr[2]), a33 = fr[3] * H.h33 + (1.0 - fr[3]);
+  const double a01 = fr[0] * fr[1] * H.h01, a02 = fr[0] * fr[2] * H.h02, a03 = fr[0] * fr[3] * H.h03;
+  const double a12 = fr[1] * fr[2] * H.h12, a13 = fr[1] * fr[3] * H.h13, a23 = fr[2] * fr[3] * H.h23;
+  // A = L D L^T, unit lower L
+  const double d0 = a00, i0 = qrcp(d0);
+  const double l10 = a01 * i0, l20 = a02 * i0, l30 = a03 * i0;
+  const double d1 = a11 - a01 * l10, i1 = qrcp(d1);
+  const double b12 = a12 - a02 * l10, b13 = a13 - a03 * l10;
+  const double l21 = b12 * i1, l31 = b13 * i1;
+  const double d2 = (a22 - a02 * l20) - b12 * l21, i2 = qrcp(d2);
+  const double b23 = (a23 - a03 * l20) - b13 * l21;
+  const double l32 = b23 * i2;
+  const double d3 = ((a33 - a03 * l30) - b13 * l31) - b23 * l32;
+  const bool pd = d0 > 0.0 && d1 > 0.0 && d2 > 0.0 && d3 > 0.0;
+  const double i3 = qrcp(d3);
+  // L y = -g_f, then D w = y, then L^T s = w
+  const double y0 = -fr[0] * g[0];
+  const double y1 = -fr[1] * g[1] - l10 * y0;
+  const double y2 = (-fr[2] * g[2] - l20 * y0) - l21 * y1;
+  const double y3 = ((-fr[3] * g[3] - l30 * y0) - l31 * y1) - l32 * y2;
+  const double s3 = y3 * i3;
+  const double s2 = y2 * i2 - l32 * s3;
+  const double s1 = (y1 * i1 - l21 * s2) - l31 * s3;
+  const double s0 = ((y0 * i0 - l10 * s1) - l20 * s2) - l30 * s3;
+  d[0] = s0; d[1] = s1; d[2] = s2; d[3] = s3;
+  return pd && (s0 * s0 + s1 * s1) + (s2 * s2 + s3 * s3) < delta * delta;
+}
+
 // Gradient and Hessian at the current iterate, kept in LDS so that a rejected trial
 // (whose own gradient and Hessian were formed with its value) costs no second
 // evaluation: slot k of the lane's 14 values at gh[k][lane] (conflict-free).
@@ -259,7 +299,7 @@ struct GHSave {
 // does without a division on the dependency chain.
 template <int BS>
 __device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
-                             const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, bool& conv) {
+                             const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, int& n_dir, bool& conv) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
   double g[4], xe[4];
@@ -308,7 +348,8 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
     }
     if (pg <= p.gtol) { conv = true; break; }
     double d[4];
-    steihaug(H, g, fr, nf, delta, d, n_cg);
+    if (newton_step_direct(H, g, fr, delta, d)) ++n_dir;
+    else steihaug(H, g, fr, nf, delta, d, n_cg);
     double sv[4];
     double sinf = 0.0, xinf = 0.0;
 #pragma unroll
@@ -407,7 +448,7 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   const int TL = n.T * n.L;
   const int idx = blk * BS + threadIdx.x;
   const bool active = idx < TL;
-  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0;
+  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0, n_dir = 0;
   const Line L = load_line(n, s, p, idx, active);
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
@@ -426,11 +467,11 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   if (active) {
     bool conv;
-    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, conv);
+    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, conv);
     if (START == START_LEARNED && !conv) {
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, conv);
+      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, conv);
     }
     // z, y of the eight rows for the per-end sums below, loaded before this lane's
     // first store so that their latency overlaps the final flows
@@ -482,18 +523,18 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
     }
   }
   // work counters: one wave-level sum per counter, added to the wave's own slot
-  unsigned long long c[5] = {(unsigned long long)n_eval, (unsigned long long)n_rej, (unsigned long long)n_cg,
-                             (unsigned long long)it, (unsigned long long)n_fb};
+  unsigned long long c[NBRC] = {(unsigned long long)n_eval, (unsigned long long)n_rej, (unsigned long long)n_cg,
+                                (unsigned long long)it, (unsigned long long)n_fb, (unsigned long long)n_dir};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < NBRC; ++k) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     // this wavefront's own slot (no atomics: the same wave owns it in every launch)
-    unsigned long long* slot = s.br_count + (size_t)((blk * BS + (int)threadIdx.x) >> 6) * 5;
+    unsigned long long* slot = s.br_count + (size_t)((blk * BS + (int)threadIdx.x) >> 6) * NBRC;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) slot[k] += c[k];
+    for (int k = 0; k < NBRC; ++k) slot[k] += c[k];
   }
 }
 

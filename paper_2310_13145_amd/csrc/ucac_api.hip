@@ -192,7 +192,7 @@ size_t carve(ucac_handle* h, char* base) {
   s.ub_nxt = a.take<double>(3 * T * G);
   s.br_iters = a.take<int>(T * L);
   s.x0 = a.take<float>(4 * T * L);
-  s.br_count = a.take<unsigned long long>(branch_waves(h) * 5);
+  s.br_count = a.take<unsigned long long>(branch_waves(h) * NBRC);
   s.red_units = 0;
   s.red_bus = s.red_units + n.G;  // one slot per unit block: at most one block per generator
   s.red_bpost = s.red_bus + bus_blocks(n);
@@ -654,7 +654,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   }
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
-      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * 5 * branch_waves(h)) != hipSuccess ||
+      hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * NBRC * branch_waves(h)) != hipSuccess ||
       hipMemset(h->st.red, 0, sizeof(double) * NACC * h->st.red_n) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
@@ -890,12 +890,12 @@ int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset) {
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
   const size_t nw = branch_waves(h);
-  std::vector<uint64_t> part(nw * 5);
-  if (nw) HIP_OR(h, hipMemcpy(part.data(), h->st.br_count, sizeof(uint64_t) * 5 * nw, hipMemcpyDeviceToHost));
-  for (int k = 0; k < 5; ++k) out[k] = 0;
+  std::vector<uint64_t> part(nw * NBRC);
+  if (nw) HIP_OR(h, hipMemcpy(part.data(), h->st.br_count, sizeof(uint64_t) * NBRC * nw, hipMemcpyDeviceToHost));
+  for (int k = 0; k < NBRC; ++k) out[k] = 0;
   for (size_t w = 0; w < nw; ++w)
-    for (int k = 0; k < 5; ++k) out[k] += part[w * 5 + k];
-  if (reset && nw) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * 5 * nw));
+    for (int k = 0; k < NBRC; ++k) out[k] += part[w * NBRC + k];
+  if (reset && nw) HIP_OR(h, hipMemset(h->st.br_count, 0, sizeof(uint64_t) * NBRC * nw));
   return UCAC_OK;
 }
 
