@@ -39,8 +39,16 @@ struct Line {
   double rpq, rva, mu, inv2mu, nu0, nu1;
 };
 
+// The line Hessian.  The flows depend on the two angles only through their
+// difference, so every term except the angle rows' rho_va on the diagonal has
+// h03 = -h02, h13 = -h12, h33 = h22 and h23 = -h22; the angle rows add rho_va to h22
+// and h33 alike.  Seven values are kept; the other three are exact negations or
+// copies.
 struct Sym4 {
-  double h00, h01, h02, h03, h11, h12, h13, h22, h23, h33;
+  double h00, h01, h02, h11, h12, h22, h23;
+  __device__ double h03() const { return -h02; }
+  __device__ double h13() const { return -h12; }
+  __device__ double h33() const { return h22; }
 };
 
 // Quotient n / d for d > 0 from the hardware reciprocal refined by two Newton
@@ -84,10 +92,12 @@ __device__ inline void flows4(const Line& L, double vi, double vj, double C, dou
   f3 = -L.Bs * vj2 + vv * (-L.Bm * C + L.G * S);
 }
 
+// H += w v v^T for v with v[3] = -v[2] (a flow gradient), on the independent entries;
+// h23 is set from h22 once the flow terms are complete.
 __device__ inline void rank1(Sym4& H, double w, const double (&v)[4]) {
-  H.h00 += w * v[0] * v[0]; H.h01 += w * v[0] * v[1]; H.h02 += w * v[0] * v[2]; H.h03 += w * v[0] * v[3];
-  H.h11 += w * v[1] * v[1]; H.h12 += w * v[1] * v[2]; H.h13 += w * v[1] * v[3];
-  H.h22 += w * v[2] * v[2]; H.h23 += w * v[2] * v[3]; H.h33 += w * v[3] * v[3];
+  H.h00 += w * v[0] * v[0]; H.h01 += w * v[0] * v[1]; H.h02 += w * v[0] * v[2];
+  H.h11 += w * v[1] * v[1]; H.h12 += w * v[1] * v[2];
+  H.h22 += w * v[2] * v[2];
 }
 
 // value, gradient and Hessian
@@ -114,7 +124,7 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
   }
   double w[4];
   double F = 0.0;
-  H = Sym4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  H = Sym4{0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const int kp = 2 * m, kq = 2 * m + 1;
@@ -145,11 +155,13 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
     Tdw += w[k] * Td[k];
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) g[i] = (w[0] * gf[0][i] + w[1] * gf[1][i]) + (w[2] * gf[2][i] + w[3] * gf[3][i]);
+  for (int i = 0; i < 3; ++i) g[i] = (w[0] * gf[0][i] + w[1] * gf[1][i]) + (w[2] * gf[2][i] + w[3] * gf[3][i]);
+  g[3] = -g[2];  // gf[k][3] = -gf[k][2]
   // weighted second derivatives of the flows
-  H.h00 += 2.0 * Aw;      H.h01 += Tw;           H.h02 += vj * Tdw;  H.h03 -= vj * Tdw;
-  H.h11 += 2.0 * Bw;      H.h12 += vi * Tdw;     H.h13 -= vi * Tdw;
-  H.h22 -= vv * Tw;       H.h23 += vv * Tw;      H.h33 -= vv * Tw;
+  H.h00 += 2.0 * Aw;      H.h01 += Tw;           H.h02 += vj * Tdw;
+  H.h11 += 2.0 * Bw;      H.h12 += vi * Tdw;
+  H.h22 -= vv * Tw;
+  H.h23 = -H.h22;
   // voltage-square and angle rows
   const double r4 = vi * vi - L.c[4], r5 = vj * vj - L.c[5];
   const double r6 = x[2] - L.c[6], r7 = x[3] - L.c[7];
@@ -160,17 +172,16 @@ __device__ inline double evaluate(const Line& L, const double (&x)[4], double (&
   g[3] += L.rva * r7;
   H.h00 += L.rva * (4.0 * vi * vi + 2.0 * r4);
   H.h11 += L.rva * (4.0 * vj * vj + 2.0 * r5);
-  H.h22 += L.rva;
-  H.h33 += L.rva;
+  H.h22 += L.rva;  // and h33
   return F;
 }
 
 // 4-term sums are formed as two pairs (a tree): a shorter dependency chain.
 __device__ inline void symv(const Sym4& H, const double (&v)[4], double (&out)[4]) {
-  out[0] = (H.h00 * v[0] + H.h01 * v[1]) + (H.h02 * v[2] + H.h03 * v[3]);
-  out[1] = (H.h01 * v[0] + H.h11 * v[1]) + (H.h12 * v[2] + H.h13 * v[3]);
+  out[0] = (H.h00 * v[0] + H.h01 * v[1]) + (H.h02 * v[2] + H.h03() * v[3]);
+  out[1] = (H.h01 * v[0] + H.h11 * v[1]) + (H.h12 * v[2] + H.h13() * v[3]);
   out[2] = (H.h02 * v[0] + H.h12 * v[1]) + (H.h22 * v[2] + H.h23 * v[3]);
-  out[3] = (H.h03 * v[0] + H.h13 * v[1]) + (H.h23 * v[2] + H.h33 * v[3]);
+  out[3] = (H.h03() * v[0] + H.h13() * v[1]) + (H.h23 * v[2] + H.h33() * v[3]);
 }
 
 __device__ inline double dot(const double (&a)[4], const double (&b)[4]) {
@@ -242,9 +253,9 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 __device__ inline bool newton_step_direct(const Sym4& H, const double (&g)[4], const double (&fr)[4], double delta,
                                           double (&d)[4]) {
   const double a00 = fr[0] * H.h00 + (1.0 - fr[0]), a11 = fr[1] * H.h11 + (1.0 - fr[1]);
-  const double a22 = fr[2] * H.h22 + (1.0 - fr[2]), a33 = fr[3] * H.h33 + (1.0 - fr[3]);
-  const double a01 = fr[0] * fr[1] * H.h01, a02 = fr[0] * fr[2] * H.h02, a03 = fr[0] * fr[3] * H.h03;
-  const double a12 = fr[1] * fr[2] * H.h12, a13 = fr[1] * fr[3] * H.h13, a23 = fr[2] * fr[3] * H.h23;
+  const double a22 = fr[2] * H.h22 + (1.0 - fr[2]), a33 = fr[3] * H.h33() + (1.0 - fr[3]);
+  const double a01 = fr[0] * fr[1] * H.h01, a02 = fr[0] * fr[2] * H.h02, a03 = fr[0] * fr[3] * H.h03();
+  const double a12 = fr[1] * fr[2] * H.h12, a13 = fr[1] * fr[3] * H.h13(), a23 = fr[2] * fr[3] * H.h23;
   // A = L D L^T, unit lower L
   const double d0 = a00, i0 = qrcp(d0);
   const double l10 = a01 * i0, l20 = a02 * i0, l30 = a03 * i0;
@@ -272,21 +283,21 @@ __device__ inline bool newton_step_direct(const Sym4& H, const double (&g)[4], c
 
 // Gradient and Hessian at the current iterate, kept in LDS so that a rejected trial
 // (whose own gradient and Hessian were formed with its value) costs no second
-// evaluation: slot k of the lane's 14 values at gh[k][lane] (conflict-free).
+// evaluation: slot k of the lane's 11 values at gh[k][lane] (conflict-free).
 template <int BS>
 struct GHSave {
   double (*gh)[BS];
   __device__ void store(const double (&g)[4], const Sym4& H) const {
     const int t = threadIdx.x;
     gh[0][t] = g[0]; gh[1][t] = g[1]; gh[2][t] = g[2]; gh[3][t] = g[3];
-    gh[4][t] = H.h00; gh[5][t] = H.h01; gh[6][t] = H.h02; gh[7][t] = H.h03; gh[8][t] = H.h11;
-    gh[9][t] = H.h12; gh[10][t] = H.h13; gh[11][t] = H.h22; gh[12][t] = H.h23; gh[13][t] = H.h33;
+    gh[4][t] = H.h00; gh[5][t] = H.h01; gh[6][t] = H.h02; gh[7][t] = H.h11;
+    gh[8][t] = H.h12; gh[9][t] = H.h22; gh[10][t] = H.h23;
   }
   __device__ void load(double (&g)[4], Sym4& H) const {
     const int t = threadIdx.x;
     g[0] = gh[0][t]; g[1] = gh[1][t]; g[2] = gh[2][t]; g[3] = gh[3][t];
-    H.h00 = gh[4][t]; H.h01 = gh[5][t]; H.h02 = gh[6][t]; H.h03 = gh[7][t]; H.h11 = gh[8][t];
-    H.h12 = gh[9][t]; H.h13 = gh[10][t]; H.h22 = gh[11][t]; H.h23 = gh[12][t]; H.h33 = gh[13][t];
+    H.h00 = gh[4][t]; H.h01 = gh[5][t]; H.h02 = gh[6][t]; H.h11 = gh[7][t];
+    H.h12 = gh[8][t]; H.h22 = gh[9][t]; H.h23 = gh[10][t];
   }
 };
 
@@ -443,7 +454,7 @@ enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
 template <int START, int BS>
 __device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
   if (s.ctl->halt) return;
-  __shared__ double gh_lds[14][BS];
+  __shared__ double gh_lds[11][BS];
   const GHSave<BS> save{gh_lds};
   const int TL = n.T * n.L;
   const int idx = blk * BS + threadIdx.x;

@@ -59,9 +59,9 @@ void launch_dp_tables(const double* tab, int G, int T, const int* tu, const int*
 // 64), reduced (16 -> 4 -> 1) while the DP slots for horizon T exceed the LDS one
 // block of bs threads may take when it shares a launch with the line kernel: at the
 // line kernel's two wavefronts per SIMD a compute unit holds 512 / bs blocks, each
-// with the line kernel's 14 * 8 * bs bytes of static LDS.
+// with the line kernel's 11 * 8 * bs bytes of static LDS.
 int units_gpb(int T, int dp_lanes, int bs) {
-  const size_t budget = (size_t)160 * 1024 * bs / 512 - (size_t)14 * 8 * bs - 256;
+  const size_t budget = (size_t)160 * 1024 * bs / 512 - (size_t)11 * 8 * bs - 256;
   int g = 256 / dp_lanes;
   while (g > 1 && dp_slot_bytes(T) * (size_t)g > budget) g = g == 16 ? 4 : 1;
   return g;
