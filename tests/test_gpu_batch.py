@@ -57,6 +57,23 @@ def test_every_mapping_bit_identical(cfg):
     b.close()
 
 
+@pytest.mark.parametrize("cfg", [(16, 256, 1), (64, 64, 0)])
+def test_long_horizon_member_bit_identical(cfg):
+    """A member with a long horizon sets the unit side's units per block for the whole
+    batch (sized by the longest horizon); every member still computes what it does
+    alone."""
+    insts = [synth.small_instance(9, 12, 3, 6, seed=501), synth.small_instance(14, 20, 5, 160, seed=502),
+             synth.small_instance(30, 45, 8, 24, seed=503)]
+    print(f"[batch] long-horizon members, T = {[i['T'] for i in insts]}, config {cfg}", flush=True)
+    ref = _single_states(insts, 10)
+    b = ucac.Batch(insts)
+    b.set_config(*cfg)
+    b.step(10)
+    for k in range(len(insts)):
+        np.testing.assert_array_equal(b.member(k).get_state(), ref[k], err_msg=f"member {k}, config {cfg}")
+    b.close()
+
+
 def test_autotune_keeps_iterate():
     insts = members()
     ref = _single_states(insts, 20)

@@ -196,6 +196,17 @@ def test_edge_cases():
     compare(g.get_state(), o.get_state(), single, 1e-8, "single_bus")
 
 
+@pytest.mark.parametrize("T", [150, 400])
+def test_long_horizon_matches_oracle(T):
+    """Horizons whose unit-side DP tables no longer fit 16 units per 256-thread block
+    (T = 150: 4 units per block; T = 400: 1): 20 iterations against the oracle."""
+    inst = synth.small_instance(14, 20, 5, T, seed=90 + T)
+    g, o = pair(inst)
+    g.step(20)
+    o.step(20)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, f"T={T}")
+
+
 def test_determinism_and_resume_bit_exact():
     inst = synth.config_instance(1)
     a = ucac.Solver(inst)
