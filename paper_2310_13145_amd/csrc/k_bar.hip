@@ -90,6 +90,27 @@ __device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, 
   return d;
 }
 
+// The consensus and next-period ramp terms of unit g at bus-side item k = t * G + g
+// (the previous relaxed commitments): weight Wp and weighted centre Sp of pbar_t,
+// and the centre tq of qbar_t.
+__device__ inline void unit_terms(const Net& n, const State& s, const Par& p, int t, int k, int g, double& Wp,
+                                  double& Sp, double& tq) {
+  const int T = n.T, G = n.G, TG = T * G;
+  const double rpq = p.rho_pq, rc = p.rho_cpl;
+  Wp = rpq;
+  Sp = rpq * (s.p[k] + s.zG[RG_G1 * TG + k] + s.yG[RG_G1 * TG + k] / rpq);
+  if (t + 1 < T) {
+    const int kn = k + G;
+    const double t5 = s.p[kn] - s.s[4 * TG + kn] + n.rd[g] * s.ubon[kn] + n.sd[g] * s.ubsd[kn] +
+                      s.zG[RG_C5 * TG + kn] + s.yG[RG_C5 * TG + kn] / rc;
+    const double t6 = s.p[kn] + s.s[5 * TG + kn] - n.ru[g] * s.ubon[k] - n.su[g] * s.ubsu[kn] +
+                      s.zG[RG_C6 * TG + kn] + s.yG[RG_C6 * TG + kn] / rc;
+    Wp += 2.0 * rc;
+    Sp += rc * t5 + rc * t6;
+  }
+  tq = s.q[k] + s.zG[RG_G2 * TG + k] + s.yG[RG_G2 * TG + k] / rpq;
+}
+
 __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
@@ -98,7 +119,7 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
   if (idx < T * N) {
     const int t = idx / N, i = idx - t * N;
-    const double rpq = p.rho_pq, rva = p.rho_va, rc = p.rho_cpl;
+    const double rpq = p.rho_pq, rva = p.rho_va;
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
@@ -128,19 +149,14 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
       }
     }
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
+    // the first two units' terms stay in registers for their updates after the solve
+    double cW[2] = {0.0, 0.0}, cS[2] = {0.0, 0.0}, cq[2] = {0.0, 0.0};
     for (int e = g0; e < g1; ++e) {
       const int g = n.gen_list[e], k = t * G + g;
-      double Wp = rpq, Sp = rpq * (s.p[k] + s.zG[RG_G1 * TG + k] + s.yG[RG_G1 * TG + k] / rpq);
-      if (t + 1 < T) {
-        const int kn = k + G;
-        const double t5 = s.p[kn] - s.s[4 * TG + kn] + n.rd[g] * s.ubon[kn] + n.sd[g] * s.ubsd[kn] +
-                          s.zG[RG_C5 * TG + kn] + s.yG[RG_C5 * TG + kn] / rc;
-        const double t6 = s.p[kn] + s.s[5 * TG + kn] - n.ru[g] * s.ubon[k] - n.su[g] * s.ubsu[kn] +
-                          s.zG[RG_C6 * TG + kn] + s.yG[RG_C6 * TG + kn] / rc;
-        Wp += 2.0 * rc;
-        Sp += rc * t5 + rc * t6;
-      }
-      const double tq = s.q[k] + s.zG[RG_G2 * TG + k] + s.yG[RG_G2 * TG + k] / rpq;
+      double Wp, Sp, tq;
+      unit_terms(n, s, p, t, k, g, Wp, Sp, tq);
+      if (e == g0) { cW[0] = Wp; cS[0] = Sp; cq[0] = tq; }
+      if (e == g0 + 1) { cW[1] = Wp; cS[1] = Sp; cq[1] = tq; }
       M11 += 1.0 / Wp;
       aT += Sp / Wp;
       M22 += 1.0 / rpq;
@@ -162,17 +178,10 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
     for (int e = g0; e < g1; ++e) {
       const int g = n.gen_list[e], k = t * G + g;
-      double Wp = rpq, Sp = rpq * (s.p[k] + s.zG[RG_G1 * TG + k] + s.yG[RG_G1 * TG + k] / rpq);
-      if (t + 1 < T) {
-        const int kn = k + G;
-        const double t5 = s.p[kn] - s.s[4 * TG + kn] + n.rd[g] * s.ubon[kn] + n.sd[g] * s.ubsd[kn] +
-                          s.zG[RG_C5 * TG + kn] + s.yG[RG_C5 * TG + kn] / rc;
-        const double t6 = s.p[kn] + s.s[5 * TG + kn] - n.ru[g] * s.ubon[k] - n.su[g] * s.ubsu[kn] +
-                          s.zG[RG_C6 * TG + kn] + s.yG[RG_C6 * TG + kn] / rc;
-        Wp += 2.0 * rc;
-        Sp += rc * t5 + rc * t6;
-      }
-      const double tq = s.q[k] + s.zG[RG_G2 * TG + k] + s.yG[RG_G2 * TG + k] / rpq;
+      double Wp, Sp, tq;
+      if (e == g0) { Wp = cW[0]; Sp = cS[0]; tq = cq[0]; }
+      else if (e == g0 + 1) { Wp = cW[1]; Sp = cS[1]; tq = cq[1]; }
+      else unit_terms(n, s, p, t, k, g, Wp, Sp, tq);
       const double pn = Sp / Wp + mu1 / Wp, qn = tq + mu2 / rpq;
       const double pold = s.pb[k], qold = s.qb[k], pv = s.p[k], qv = s.q[k];
       RowZY r1 = row_load(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k);

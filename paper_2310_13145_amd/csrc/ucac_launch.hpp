@@ -16,13 +16,8 @@ void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st)
 void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st);
 
 // Blocks of each kernel's single-instance grid (what one member contributes to a
-// grouped launch); dp_lanes is the lanes per generator of the DP (16 or 64),
-// branch_block the line kernel's block size (64 or 256).
-struct Tuning {
-  int dp_lanes = 64;
-  int branch_block = 256;
-};
-// K_ITER kernels per iteration; K_LAMBDA flushes a pending multiplier update after a call
+// grouped launch).  K_ITER kernels per iteration; K_LAMBDA flushes a pending
+// multiplier update after a call.
 // K_FRONT: the unit side and the lines in one launch (the units' and the lines' block
 // tables side by side); the iteration graph runs K_FRONT, K_BUS, K_POST, K_FINALIZE.
 enum { K_UNITS, K_BRANCH, K_BUS, K_POST, K_FINALIZE, K_ITER, K_LAMBDA = K_ITER, K_COUNT, K_FRONT = K_COUNT };
