@@ -106,6 +106,8 @@ def lib():
         L.orc_branch_F.restype = C.c_double
         L.orc_branch_solve.argtypes = [vp, vp, C.c_int, C.c_double, ip]
         L.orc_branch_solve.restype = C.c_int
+        L.orc_branch_trial.argtypes = [vp, vp, C.c_double, vp]
+        L.orc_branch_trial.restype = C.c_double
         L.orc_line_admittance.argtypes = [C.c_double, C.c_double, C.c_double, vp]
         L.orc_line_flows.argtypes = [vp, vp, vp]
         _lib = L
@@ -273,6 +275,16 @@ def branch_solve(v, x0, max_iter=50, gtol=1e-8):
     cg = C.c_int32(0)
     it = lib().orc_branch_solve(_ptr(v), _ptr(x), int(max_iter), float(gtol), C.byref(cg))
     return x, it, cg.value
+
+
+def branch_trial(v, x, delta):
+    """Trial point of one projected trust-region Newton iteration from x (gradient,
+    Hessian and free set taken at x) and the model value q(xt - x)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xt = np.zeros(4)
+    q = lib().orc_branch_trial(_ptr(v), _ptr(x), float(delta), _ptr(xt))
+    return xt, q
 
 
 def line_admittance(r, x, b):

@@ -291,9 +291,63 @@ static void steihaug(double H[4][4], const double *g, const int *fr, double delt
 
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* Projected trust-region Newton (Nocedal & Wright Alg. 4.1 with the step of
- * Alg. 7.2 on the free set, then a projection onto the box).  Returns the number
- * of Newton iterations taken; x holds the start on entry and the result on exit. */
+/* The trial point of one projected trust-region Newton iteration from x with
+ * gradient g, Hessian H, free set fr and radius delta: the Steihaug step d of
+ * Alg. 7.2 on the free set, projected onto the box.  Where the full step leaves the
+ * box and its projection fails the sufficient-decrease test of the quadratic model,
+ * q(s) <= mu0 g.s with mu0 = 0.01, the step instead stops at the first break point
+ * of the ray x + alpha d (the projected search of Lin and More's TRON, the solver
+ * the paper hands the line subproblem to): the model decreases along the ray up to
+ * there, and the variable whose bound is reached first is placed on it.  Writes the
+ * trial point xt and step s = xt - x; returns the model value q(s). */
+static double trial_point(const branch_pb *b, const double *x, const double *g, double H[4][4], const int *fr,
+                          double delta, double *xt, double *s, int *cg_its) {
+  double d[4];
+  steihaug(H, g, fr, delta, d, cg_its);
+  int left_box = 0;
+  for (int i = 0; i < 4; ++i) {
+    double xd = x[i] + d[i];
+    if (xd < b->lo[i] || xd > b->hi[i]) left_box = 1;
+    xt[i] = clampd(xd, b->lo[i], b->hi[i]);
+    s[i] = xt[i] - x[i];
+  }
+  double Hs[4];
+  for (int i = 0; i < 4; ++i) {
+    Hs[i] = 0.0;
+    for (int k = 0; k < 4; ++k) Hs[i] += H[i][k] * s[k];
+  }
+  double gs = dot4(g, s);
+  double q = gs + 0.5 * dot4(s, Hs);
+  if (left_box && q > 0.01 * gs) {
+    /* projected search: the first break point, where a component moving towards a
+     * bound it is not on reaches it (at most the full step) */
+    double alpha = 1.0;
+    int first = -1;
+    for (int i = 0; i < 4; ++i) {
+      double brk;
+      if (d[i] > 0.0 && x[i] < b->hi[i]) brk = (b->hi[i] - x[i]) / d[i];
+      else if (d[i] < 0.0 && x[i] > b->lo[i]) brk = (b->lo[i] - x[i]) / d[i];
+      else continue;
+      if (brk < alpha) { alpha = brk; first = i; }
+    }
+    for (int i = 0; i < 4; ++i) {
+      if (i == first) xt[i] = d[i] > 0.0 ? b->hi[i] : b->lo[i];
+      else xt[i] = clampd(x[i] + alpha * d[i], b->lo[i], b->hi[i]);
+      s[i] = xt[i] - x[i];
+    }
+    for (int i = 0; i < 4; ++i) {
+      Hs[i] = 0.0;
+      for (int k = 0; k < 4; ++k) Hs[i] += H[i][k] * s[k];
+    }
+    gs = dot4(g, s);
+    q = gs + 0.5 * dot4(s, Hs);
+  }
+  return q;
+}
+
+/* Projected trust-region Newton (Nocedal & Wright Alg. 4.1 with the trial point
+ * above).  Returns the number of Newton iterations taken; x holds the start on entry
+ * and the result on exit. */
 static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol, int *cg_total) {
   double g[4], H[4][4];
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], b->lo[i], b->hi[i]);
@@ -311,22 +365,15 @@ static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol
       if (fr[i] && fabs(g[i]) > pg) pg = fabs(g[i]);
     }
     if (pg <= gtol) break;
-    double d[4], xt[4], s[4];
-    steihaug(H, g, fr, delta, d, &cg_its);
+    double xt[4], s[4];
+    double q = trial_point(b, x, g, H, fr, delta, xt, s, &cg_its);
     double sinf = 0.0, xinf = 0.0;
     for (int i = 0; i < 4; ++i) {
-      xt[i] = clampd(x[i] + d[i], b->lo[i], b->hi[i]);
-      s[i] = xt[i] - x[i];
       if (fabs(s[i]) > sinf) sinf = fabs(s[i]);
       if (fabs(x[i]) > xinf) xinf = fabs(x[i]);
     }
     if (sinf <= 1e-15 * (1.0 + xinf)) break;
-    double Hs[4];
-    for (int i = 0; i < 4; ++i) {
-      Hs[i] = 0.0;
-      for (int k = 0; k < 4; ++k) Hs[i] += H[i][k] * s[k];
-    }
-    double pred = -(dot4(g, s) + 0.5 * dot4(s, Hs));
+    double pred = -q;
     double Ft = branch_F(b, xt);
     /* a predicted decrease below the rounding level of F cannot be judged by the
      * actual decrease (both are noise): take the Newton step as agreeing */
@@ -1198,6 +1245,17 @@ int orc_branch_solve(const double *v, double *x, int max_iter, double gtol, int 
   branch_pb b;
   unpack_branch(v, &b);
   return branch_solve(&b, x, max_iter, gtol, cg_its);
+}
+
+/* One trial point from x with radius delta (evaluates g and H at x itself). */
+double orc_branch_trial(const double *v, const double *x, double delta, double *xt) {
+  branch_pb b;
+  unpack_branch(v, &b);
+  double g[4], H[4][4], s[4];
+  int fr[4], cg = 0;
+  branch_eval(&b, x, g, H);
+  for (int i = 0; i < 4; ++i) fr[i] = !((x[i] <= b.lo[i] && g[i] > 0.0) || (x[i] >= b.hi[i] && g[i] < 0.0));
+  return trial_point(&b, x, g, H, fr, delta, xt, s, &cg);
 }
 
 void orc_line_admittance(double r, double x, double b, double *adm) { line_admittance(r, x, b, adm); }

@@ -301,6 +301,30 @@ struct GHSave {
   }
 };
 
+// The projected search of TRON (Lin and More), the solver the paper hands the line
+// subproblem to, taken where the full step d leaves the box and its projection fails
+// the model's sufficient-decrease test: the step stops at the first break point of
+// the ray x + alpha d, alpha <= 1, over the variables moving towards a bound they
+// are not on; the variable that sets alpha is placed on its bound.  Rare (a few lanes
+// per launch), so the quotients are plain IEEE divisions.
+__device__ inline void projected_search(const double (&x)[4], const double (&d)[4], const double (&lo)[4],
+                                        const double (&hi)[4], double (&xe)[4], double (&sv)[4]) {
+  double alpha = 1.0;
+  int first = -1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool up = d[i] > 0.0 && x[i] < hi[i], down = d[i] < 0.0 && x[i] > lo[i];
+    if (!(up || down)) continue;
+    const double brk = ((up ? hi[i] : lo[i]) - x[i]) / d[i];
+    if (brk < alpha) { alpha = brk; first = i; }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    xe[i] = i == first ? (d[i] > 0.0 ? hi[i] : lo[i]) : clampd(x[i] + alpha * d[i], lo[i], hi[i]);
+    sv[i] = xe[i] - x[i];
+  }
+}
+
 // Projected trust-region Newton from x (in place).  Returns the iterations taken;
 // conv is set when it stopped at the projected-gradient tolerance.  There is one
 // evaluation site: value, gradient and Hessian are formed at every trial point in
@@ -362,18 +386,32 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
     if (newton_step_direct(H, g, fr, delta, d)) ++n_dir;
     else steihaug(H, g, fr, nf, delta, d, n_cg);
     double sv[4];
+    bool left_box = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double xd = x[i] + d[i];
+      left_box = left_box || xd < lo[i] || xd > hi[i];
+      xe[i] = clampd(xd, lo[i], hi[i]);
+      sv[i] = xe[i] - x[i];
+    }
+    double Hs[4];
+    symv(H, sv, Hs);
+    double gs = dot(g, sv);
+    double q = gs + 0.5 * dot(sv, Hs);
+    if (left_box && q > 0.01 * gs) {
+      projected_search(x, d, lo, hi, xe, sv);
+      symv(H, sv, Hs);
+      gs = dot(g, sv);
+      q = gs + 0.5 * dot(sv, Hs);
+    }
     double sinf = 0.0, xinf = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      xe[i] = clampd(x[i] + d[i], lo[i], hi[i]);
-      sv[i] = xe[i] - x[i];
       sinf = fmax(sinf, fabs(sv[i]));
       xinf = fmax(xinf, fabs(x[i]));
     }
     if (sinf <= 1e-15 * (1.0 + xinf)) break;
-    double Hs[4];
-    symv(H, sv, Hs);
-    pred = -(dot(g, sv) + 0.5 * dot(sv, Hs));
+    pred = -q;
     snorm = sqrt(dot(sv, sv));
     trial = true;
     ++it;

@@ -102,13 +102,85 @@ def test_branch_solve_is_stationary_and_minimal():
         lo, hi = v[9:13], v[13:17]
         free = ~(((x <= lo) & (g > 0)) | ((x >= hi) & (g < 0)))
         assert it < 50
-        assert np.max(np.abs(g[free])) <= gtol
         Hf = H[np.ix_(free, free)]
+        # the method stops at the gradient tolerance, or where its step falls below
+        # 1e-15 (1 + |x|_inf): there the free-set Newton step is below the resolution
+        # of x, and the gradient may sit at its rounding level just above gtol
+        pg = np.max(np.abs(g[free]))
+        step = np.max(np.abs(np.linalg.solve(Hf, g[free])))
+        assert pg <= gtol or step <= 2e-15 * (1.0 + np.max(np.abs(x))), (trial, pg, step)
         assert np.linalg.eigvalsh(Hf).min() >= -1e-6 * np.abs(Hf).max()
         # no better point nearby (generic bounded quasi-Newton from the oracle's answer)
         res = minimize(lambda xx: F_numpy(v, rxb, xx), x, method="L-BFGS-B", bounds=list(zip(lo, hi)),
                        options=dict(ftol=1e-15, gtol=1e-12))
         assert res.fun >= F - 1e-9 * max(1.0, abs(F))
+
+
+def test_branch_trial_projected_search():
+    """One trial point of the line Newton where the free Hessian is positive definite
+    and the Newton step lies inside the region (Steihaug's step is the Newton step
+    there).  A step that stays in the box is taken whole.  One that leaves it is
+    projected; if that projection fails the model's sufficient-decrease test
+    (q(s) <= 0.01 g.s), the trial stops where the ray x + alpha d first reaches a bound
+    it is moving towards (TRON's projected search, found here by bisection on alpha),
+    with that variable exactly on its bound and, where the trial lies on the ray, the
+    model strictly decreased.  The
+    sample holds projections whose model value lies in (0.01 g.s, 0]: a decrease, but
+    too small, so they are searched.  (The variable that sets alpha is also placed on
+    its bound explicitly, a guard: x + alpha d lands on it exactly in every case seen.)"""
+    rng = np.random.default_rng(11)
+    seen = {"inside": 0, "clip": 0, "search": 0, "small_decrease": 0}
+    for trial in range(8000):
+        v, _ = random_branch(rng, rate=rng.choice([0.5, 2.5]))
+        v[9:11] = 0.95
+        v[13:15] = 1.05
+        lo, hi = v[9:13], v[13:17]
+        x = np.array([rng.choice([0.951, 1.049]) + rng.normal(scale=0.002), rng.uniform(0.96, 1.04),
+                      rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3)])
+        x = np.clip(x, lo, hi)
+        F, g, H = oracle.branch_eval(v, x)
+        fr = ~(((x <= lo) & (g > 0)) | ((x >= hi) & (g < 0)))
+        Hf = H[np.ix_(fr, fr)]
+        if np.linalg.eigvalsh(Hf).min() <= 0:
+            continue
+        # (CG and the direct solve below agree to about 1e-12 on these Hessians; the
+        # three cases differ at the scale of the step)
+        d = np.zeros(4)
+        d[fr] = -np.linalg.solve(Hf, g[fr])
+        delta = 10.0
+        if np.linalg.norm(d) >= 0.5 * delta:
+            continue
+        xt, q = oracle.branch_trial(v, x, delta)
+        model = lambda st: g @ st + 0.5 * st @ H @ st
+        xd = x + d
+        if not np.any((xd < lo) | (xd > hi)):
+            seen["inside"] += 1
+            np.testing.assert_allclose(xt, xd, rtol=0, atol=1e-9)
+            continue
+        sc = np.clip(xd, lo, hi) - x
+        if model(sc) <= 0.01 * (g @ sc):
+            seen["clip"] += 1
+            np.testing.assert_allclose(xt, x + sc, rtol=0, atol=1e-9)
+            continue
+        seen["search"] += 1
+        seen["small_decrease"] += model(sc) <= 0.0
+        # components that move towards a bound they are not on
+        mv = ((d > 0) & (x < hi)) | ((d < 0) & (x > lo))
+        inside = lambda a: np.all(((x + a * d) >= lo - 1e-300) | ~mv) and np.all(((x + a * d) <= hi) | ~mv)
+        a0, a1 = 0.0, 1.0
+        for _ in range(200):
+            am = 0.5 * (a0 + a1)
+            a0, a1 = (am, a1) if inside(am) else (a0, am)
+        expect = np.clip(x + a0 * d, lo, hi)
+        np.testing.assert_allclose(xt, expect, rtol=0, atol=1e-9)
+        on = [(i, xt[i] == (hi[i] if d[i] > 0 else lo[i])) for i in range(4) if mv[i]]
+        assert any(hit for _, hit in on), (trial, xt, lo, hi)
+        assert q == pytest.approx(model(xt - x), rel=1e-9, abs=1e-12)
+        # the model decreases along the ray; where a variable on a bound is pushed
+        # outwards its projection leaves the ray, and the ratio test decides as before
+        if not np.any(((d > 0) & (x >= hi)) | ((d < 0) & (x <= lo))):
+            assert model(xt - x) < 0.0
+    assert min(seen.values()) >= 3, seen
 
 
 # --------------------------------------------------------------------------------
