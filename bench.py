@@ -39,6 +39,8 @@ FLOP_CG = 80         # one Steihaug-Toint CG iteration on the 4x4 system
 FLOP_DIRECT = 110    # one Newton step by the 4x4 LDL^T factorization (free-set assembly, 4 refined
                      # reciprocals, elimination, triangular solves, length test)
 FLOP_NEWTON = 80     # per trust-region iteration: projection, predicted reduction, ratio, radius
+FLOP_SEARCH = 64     # one projected search: four break points, the new trial point and step, and the
+                     # model value at it (Hessian product, two dot products)
 FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, final flows, nu update,
                      # the bus QP's per-end sums
 
@@ -63,8 +65,8 @@ BYTES_BUS_POST = 8 * 64     # per (line, t), both ends: flows, targets, bus resu
 # mesh2000_T24 bench command), each scaled by the ratio of true to counted bytes of a
 # plain copy kernel of known size.  They describe the kernel source they were taken
 # on (hash below) and are reported as null once that source has changed.
-BRANCH_COUNTERS = {"source_sha256": "f82667f44b141e614e269e396967cdd8c62b066cd798393d78c663056e016133",
-                   "fetch_kib": 8023.7, "write_kib": 11192.5, "fetch_scale": 2.0, "write_scale": 1.0}
+BRANCH_COUNTERS = {"source_sha256": "c408f2d2cba7d2d052e24f35a4b15ea4681036c6a40c00ec9b1af2d5891e7bc7",
+                   "fetch_kib": 8042.1, "write_kib": 11183.6, "fetch_scale": 2.0, "write_scale": 1.0}
 BRANCH_SOURCES = ("k_branch.hip", "ucac_mlp.hpp")  # the line kernel's own code
 
 
@@ -349,7 +351,8 @@ def main():
     # only the value at rejected ones, which is what is counted
     full = cnt["evals"] - cnt["rejected"]
     flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
-                        cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON) / args.steps + lanes * FLOP_LANE
+                        cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON +
+                        cnt["searches"] * FLOP_SEARCH) / args.steps + lanes * FLOP_LANE
     br_s = branch_dispatch_ms * 1e-3
     achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
@@ -383,7 +386,8 @@ def main():
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": branch_traffic(),
                      "flops_per_launch": flops_per_launch, "launch_ms": branch_dispatch_ms,
                      "launch_ms_between_events": ktimes["branch"],
-                     "newton_iters_per_solve": cnt["newton"] / args.steps / lanes},
+                     "newton_iters_per_solve": cnt["newton"] / args.steps / lanes,
+                     "projected_searches_per_launch": cnt["searches"] / args.steps},
         "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps},
         "kernels_ms": ktimes,
         "profiled_ms_per_step": prof_ms_per_step,

@@ -174,7 +174,10 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
  * learned starts that fell back to the flat start, out[5] Newton steps taken
  * from the direct 4x4 factorization instead of CG (the free-subspace Hessian
  * positive definite and the step inside the trust region, where CG returns the
- * same step); out has 6 slots.  reset != 0 zeroes them after reading. */
+ * same step), out[6] projected searches (a step that left the box and whose
+ * projection failed the model's sufficient-decrease test, stopped instead at the
+ * first bound its ray reaches); out has 7 slots.  reset != 0 zeroes them after
+ * reading. */
 int ucac_branch_counters(ucac_handle* h, uint64_t* out, int32_t reset);
 
 /* After ucac_solve (or ucac_step): first_iter[m] (m = 0, 1, 2) receives the first

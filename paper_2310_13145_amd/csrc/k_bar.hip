@@ -111,6 +111,67 @@ __device__ inline void unit_terms(const Net& n, const State& s, const Par& p, in
   tq = s.q[k] + s.zG[RG_G2 * TG + k] + s.yG[RG_G2 * TG + k] / rpq;
 }
 
+// A unit's data as the bus solve and its update need them: the consensus and ramp
+// terms, the previous bus-side values, its own p and q, and its two coupling rows.
+struct UnitPre {
+  int k;
+  double Wp, Sp, tq, pold, qold, pv, qv;
+  RowZY r1, r2;
+};
+
+// The values unit g at item k = t * G + g contributes, loaded without arithmetic so
+// that the loads stay in flight while other work proceeds (the next-period values
+// come from k itself in the last period, and are then unused).
+struct UnitRaw {
+  int k;
+  double p, q, pb, qb, rd, sd, ru, su, ubon;
+  RowZY r1, r2;
+  double pn, s4n, s5n, ubonn, ubsdn, ubsun, z5n, y5n, z6n, y6n;
+};
+
+__device__ inline UnitRaw unit_raw(const Net& n, const State& s, int t, int g) {
+  const int T = n.T, G = n.G, TG = T * G;
+  UnitRaw r;
+  const int k = t * G + g, kn = t + 1 < T ? k + G : k;
+  r.k = k;
+  r.p = s.p[k]; r.q = s.q[k]; r.pb = s.pb[k]; r.qb = s.qb[k];
+  r.rd = n.rd[g]; r.sd = n.sd[g]; r.ru = n.ru[g]; r.su = n.su[g];
+  r.ubon = s.ubon[k];
+  r.r1 = row_load(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k);
+  r.r2 = row_load(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k);
+  r.pn = s.p[kn]; r.s4n = s.s[4 * TG + kn]; r.s5n = s.s[5 * TG + kn];
+  r.ubonn = s.ubon[kn]; r.ubsdn = s.ubsd[kn]; r.ubsun = s.ubsu[kn];
+  r.z5n = s.zG[RG_C5 * TG + kn]; r.y5n = s.yG[RG_C5 * TG + kn];
+  r.z6n = s.zG[RG_C6 * TG + kn]; r.y6n = s.yG[RG_C6 * TG + kn];
+  return r;
+}
+
+// unit_terms on loaded values: the same operations in the same order.
+__device__ inline UnitPre unit_pre(const UnitRaw& r, const Par& p, int t, int T) {
+  const double rpq = p.rho_pq, rc = p.rho_cpl;
+  UnitPre u;
+  u.k = r.k;
+  u.Wp = rpq;
+  u.Sp = rpq * (r.p + r.r1.z + r.r1.y / rpq);
+  if (t + 1 < T) {
+    const double t5 = r.pn - r.s4n + r.rd * r.ubonn + r.sd * r.ubsdn + r.z5n + r.y5n / rc;
+    const double t6 = r.pn + r.s5n - r.ru * r.ubon - r.su * r.ubsun + r.z6n + r.y6n / rc;
+    u.Wp += 2.0 * rc;
+    u.Sp += rc * t5 + rc * t6;
+  }
+  u.tq = r.q + r.r2.z + r.r2.y / rpq;
+  u.pold = r.pb; u.qold = r.qb; u.pv = r.p; u.qv = r.q;
+  u.r1 = r.r1; u.r2 = r.r2;
+  return u;
+}
+
+// One lane per (bus, t).  The loads form three dependent rounds: (1) the bus's own
+// values and its incidence ranges; (2) the first unit's index; (3) that unit's terms,
+// rows and previous values (kept in registers through the solve and the update)
+// together with the sums of up to eight line ends.  The end loads are
+// unconditional (clamped indices; the contributions of unused slots are selected away
+// as +0.0, which leaves every sum exactly as if they were skipped), so that none of
+// them waits behind another; the sums keep the incidence order.
 __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const int N = n.N, G = n.G, T = n.T;
@@ -122,54 +183,62 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double rpq = p.rho_pq, rva = p.rho_va;
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
+    // round 1
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
+    const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
+    const double wold = s.wb[idx], thold = s.thb[idx];
+    const double gsh = n.gs[i], bsh = n.bs[i], Pd = n.Pd[idx], Qd = n.Qd[idx];
+    // round 2: the first unit's index; round 3: its data, issued before the end sums'
+    // loads (which need only round 1) so that those travel with them
+    const int nu = g1 - g0;
+    UnitRaw u0raw;
+    if (nu > 0) u0raw = unit_raw(n, s, t, n.gen_list[g0]);
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
     const double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;
-    // four ends' sums loaded per round (all loads in flight), then added in order
-    for (int e = e0; e < e1; e += 4) {
-      double q[4][4];
+    constexpr int ER = 8;  // ends per round: every bus of the benchmark meshes in one
+    for (int e = e0; e < e1; e += ER) {
+      double q[ER][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < ER; ++j) {
         const double* src = eb + (size_t)(e + j < e1 ? e + j : e0) * 4;
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[j][c] = src[c];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (e + j >= e1) break;
-        M11 += 1.0 / rpq;
-        aT -= q[j][0];
-        M22 += 1.0 / rpq;
-        bT -= q[j][1];
-        Ww += rva;
-        Sw += rva * q[j][2];
-        Wt += rva;
-        St += rva * q[j][3];
+      for (int j = 0; j < ER; ++j) {
+        const bool on = e + j < e1;
+        M11 += on ? 1.0 / rpq : 0.0;
+        aT -= on ? q[j][0] : 0.0;
+        M22 += on ? 1.0 / rpq : 0.0;
+        bT -= on ? q[j][1] : 0.0;
+        Ww += on ? rva : 0.0;
+        Sw += on ? rva * q[j][2] : 0.0;
+        Wt += on ? rva : 0.0;
+        St += on ? rva * q[j][3] : 0.0;
       }
     }
-    const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
-    // the first two units' terms stay in registers for their updates after the solve
-    double cW[2] = {0.0, 0.0}, cS[2] = {0.0, 0.0}, cq[2] = {0.0, 0.0};
+    UnitPre u0;
+    if (nu > 0) u0 = unit_pre(u0raw, p, t, T);
     for (int e = g0; e < g1; ++e) {
-      const int g = n.gen_list[e], k = t * G + g;
       double Wp, Sp, tq;
-      unit_terms(n, s, p, t, k, g, Wp, Sp, tq);
-      if (e == g0) { cW[0] = Wp; cS[0] = Sp; cq[0] = tq; }
-      if (e == g0 + 1) { cW[1] = Wp; cS[1] = Sp; cq[1] = tq; }
+      if (e == g0) { Wp = u0.Wp; Sp = u0.Sp; tq = u0.tq; }
+      else {
+        const int g = n.gen_list[e];
+        unit_terms(n, s, p, t, t * G + g, g, Wp, Sp, tq);
+      }
       M11 += 1.0 / Wp;
       aT += Sp / Wp;
       M22 += 1.0 / rpq;
       bT += tq;
     }
-    const double wold = s.wb[idx], thold = s.thb[idx];
     const bool has_w = Ww > 0.0;
     const double tauw = has_w ? Sw / Ww : wold;
-    const double aw = has_w ? -n.gs[i] : 0.0, bw = has_w ? n.bs[i] : 0.0;
+    const double aw = has_w ? -gsh : 0.0, bw = has_w ? bsh : 0.0;
     if (has_w) { M11 += aw * aw / Ww; M12 += aw * bw / Ww; M22 += bw * bw / Ww; }
     aT += aw * tauw;
     bT += bw * tauw;
-    const double r1 = n.Pd[idx] - aT, r2 = n.Qd[idx] - bT;
+    const double r1 = Pd - aT, r2 = Qd - bT;
     const double det = M11 * M22 - M12 * M12;
     const double mu1 = (M22 * r1 - M12 * r2) / det;
     const double mu2 = (M11 * r2 - M12 * r1) / det;
@@ -177,22 +246,15 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double thnew = (i == n.ref) ? 0.0 : (Wt > 0.0 ? St / Wt : thold);
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
     for (int e = g0; e < g1; ++e) {
-      const int g = n.gen_list[e], k = t * G + g;
-      double Wp, Sp, tq;
-      if (e == g0) { Wp = cW[0]; Sp = cS[0]; tq = cq[0]; }
-      else if (e == g0 + 1) { Wp = cW[1]; Sp = cS[1]; tq = cq[1]; }
-      else unit_terms(n, s, p, t, k, g, Wp, Sp, tq);
-      const double pn = Sp / Wp + mu1 / Wp, qn = tq + mu2 / rpq;
-      const double pold = s.pb[k], qold = s.qb[k], pv = s.p[k], qv = s.q[k];
-      RowZY r1 = row_load(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k);
-      RowZY r2 = row_load(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k);
-      rd = nmax(rd, nmax(fabs(pn - pold), fabs(qn - qold)));
-      row_update(r1, pv - pn, rpq, beta, lu, rp, rin, zinf);
-      row_update(r2, qv - qn, rpq, beta, lu, rp, rin, zinf);
-      s.pb[k] = pn;
-      s.qb[k] = qn;
-      row_store(r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, k, lu);
-      row_store(r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, k, lu);
+      UnitPre v = e == g0 ? u0 : unit_pre(unit_raw(n, s, t, n.gen_list[e]), p, t, T);
+      const double pn = v.Sp / v.Wp + mu1 / v.Wp, qn = v.tq + mu2 / rpq;
+      rd = nmax(rd, nmax(fabs(pn - v.pold), fabs(qn - v.qold)));
+      row_update(v.r1, v.pv - pn, rpq, beta, lu, rp, rin, zinf);
+      row_update(v.r2, v.qv - qn, rpq, beta, lu, rp, rin, zinf);
+      s.pb[v.k] = pn;
+      s.qb[v.k] = qn;
+      row_store(v.r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, v.k, lu);
+      row_store(v.r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, v.k, lu);
     }
     s.wb[idx] = wnew;
     s.thb[idx] = thnew;

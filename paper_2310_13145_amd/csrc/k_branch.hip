@@ -334,7 +334,8 @@ __device__ inline void projected_search(const double (&x)[4], const double (&d)[
 // does without a division on the dependency chain.
 template <int BS>
 __device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
-                             const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, int& n_dir, bool& conv) {
+                             const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, int& n_dir, int& n_srch,
+                             bool& conv) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
   double g[4], xe[4];
@@ -399,6 +400,7 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
     double gs = dot(g, sv);
     double q = gs + 0.5 * dot(sv, Hs);
     if (left_box && q > 0.01 * gs) {
+      ++n_srch;
       projected_search(x, d, lo, hi, xe, sv);
       symv(H, sv, Hs);
       gs = dot(g, sv);
@@ -497,7 +499,7 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   const int TL = n.T * n.L;
   const int idx = blk * BS + threadIdx.x;
   const bool active = idx < TL;
-  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0, n_dir = 0;
+  int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0, n_dir = 0, n_srch = 0;
   const Line L = load_line(n, s, p, idx, active);
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
@@ -516,11 +518,11 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   if (active) {
     bool conv;
-    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, conv);
+    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
     if (START == START_LEARNED && !conv) {
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, conv);
+      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
     }
     // z, y of the eight rows for the per-end sums below, loaded before this lane's
     // first store so that their latency overlaps the final flows
@@ -573,7 +575,8 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   // work counters: one wave-level sum per counter, added to the wave's own slot
   unsigned long long c[NBRC] = {(unsigned long long)n_eval, (unsigned long long)n_rej, (unsigned long long)n_cg,
-                                (unsigned long long)it, (unsigned long long)n_fb, (unsigned long long)n_dir};
+                                (unsigned long long)it, (unsigned long long)n_fb, (unsigned long long)n_dir,
+                                (unsigned long long)n_srch};
 #pragma unroll
   for (int k = 0; k < NBRC; ++k) {
 #pragma unroll

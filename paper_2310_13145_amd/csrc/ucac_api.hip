@@ -24,13 +24,33 @@ thread_local std::string g_create_error;
 // next chunk is already queued while the host reads the previous one.
 constexpr int SOLVE_CHUNK = 32;
 
-// Iterations captured in one graph: consecutive iterations inside a graph start
-// without the per-graph launch gap (about 9 us at 2,000 buses; 16 iterations per
-// graph measured 1.5 % faster per iteration than 4, 8 in between).  Iterations
-// after convergence in solve mode return at kernel entry, so running a few more is
-// harmless.  SOLVE_CHUNK is a multiple of it.
-constexpr int GRAPH_UNROLL = 16;
-static_assert(SOLVE_CHUNK % GRAPH_UNROLL == 0, "solve chunks are whole graphs");
+// Iterations are captured in graphs of 64, 16, 4 and 1 iterations, and n
+// iterations are enqueued largest graph first (500 = 7 x 64 + 3 x 16 + 4: 11
+// launches).  Consecutive iterations inside a graph start without the per-graph
+// launch gap (about 9 us at 2,000 buses; 16 iterations per graph measured 1.5 %
+// faster per iteration than 4).  Iterations after convergence in solve mode return
+// at kernel entry; a solve chunk (32) runs as two graphs of 16.
+constexpr int N_GRAPHS = 4;
+constexpr int GRAPH_SIZES[N_GRAPHS] = {64, 16, 4, 1};
+
+struct GraphSet {
+  hipGraph_t g[N_GRAPHS] = {};
+  hipGraphExec_t x[N_GRAPHS] = {};
+  void clear() {
+    for (int j = 0; j < N_GRAPHS; ++j) {
+      if (x[j]) (void)hipGraphExecDestroy(x[j]);
+      if (g[j]) (void)hipGraphDestroy(g[j]);
+      x[j] = nullptr;
+      g[j] = nullptr;
+    }
+  }
+  hipError_t launch(int n, hipStream_t st) const {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < N_GRAPHS && e == hipSuccess; ++j)
+      for (; n >= GRAPH_SIZES[j] && e == hipSuccess; n -= GRAPH_SIZES[j]) e = hipGraphLaunch(x[j], st);
+    return e;
+  }
+};
 
 struct HostGen {
   std::vector<double> k2, k1, cnl, csu, csd;
@@ -53,9 +73,7 @@ struct ucac_handle {
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;      // pinned staging of the control block
   double* h_sc = nullptr;    // pinned staging of the scalars
-  hipGraph_t graph = nullptr, graph_u = nullptr;
-  hipGraphExec_t exec = nullptr;    // one iteration
-  hipGraphExec_t exec_u = nullptr;  // GRAPH_UNROLL iterations back to back
+  GraphSet graphs;  // the iteration captured GRAPH_SIZES[j] times back to back
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
@@ -480,32 +498,23 @@ hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where,
 }
 
 int build_graph(ucac_handle* h) {
-  if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
-  if (h->exec_u) { (void)hipGraphExecDestroy(h->exec_u); h->exec_u = nullptr; }
-  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
-  if (h->graph_u) { (void)hipGraphDestroy(h->graph_u); h->graph_u = nullptr; }
-  for (int reps : {1, GRAPH_UNROLL}) {
+  h->graphs.clear();
+  for (int j = 0; j < N_GRAPHS; ++j) {
     (void)hipGetLastError();
     HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
     const char* where = "";
     hipError_t le = hipSuccess;
-    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_iteration(h, h->own, &where);
-    hipGraph_t& g = reps == 1 ? h->graph : h->graph_u;
-    const hipError_t ce = hipStreamEndCapture(h->own, &g);
+    for (int r = 0; r < GRAPH_SIZES[j] && le == hipSuccess; ++r) le = enqueue_iteration(h, h->own, &where);
+    const hipError_t ce = hipStreamEndCapture(h->own, &h->graphs.g[j]);
     if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
     if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-    HIP_OR(h, hipGraphInstantiate(reps == 1 ? &h->exec : &h->exec_u, g, nullptr, nullptr, 0));
+    HIP_OR(h, hipGraphInstantiate(&h->graphs.x[j], h->graphs.g[j], nullptr, nullptr, 0));
   }
   return UCAC_OK;
 }
 
-// Enqueue n iterations: GRAPH_UNROLL at a time, the rest one by one.
-hipError_t launch_iterations(ucac_handle* h, int n) {
-  hipError_t e = hipSuccess;
-  for (; n >= GRAPH_UNROLL && e == hipSuccess; n -= GRAPH_UNROLL) e = hipGraphLaunch(h->exec_u, h->stream);
-  for (; n > 0 && e == hipSuccess; --n) e = hipGraphLaunch(h->exec, h->stream);
-  return e;
-}
+// Enqueue n iterations, largest graph first.
+hipError_t launch_iterations(ucac_handle* h, int n) { return h->graphs.launch(n, h->stream); }
 
 // Write the host-owned control fields (never inside a captured graph).
 int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
@@ -1248,10 +1257,7 @@ void ucac_destroy(ucac_handle* h) {
   if (!h) return;
   (void)hipSetDevice(h->par.device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->exec) (void)hipGraphExecDestroy(h->exec);
-  if (h->exec_u) (void)hipGraphExecDestroy(h->exec_u);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  if (h->graph_u) (void)hipGraphDestroy(h->graph_u);
+  h->graphs.clear();
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -1276,8 +1282,7 @@ struct ucac_batch {
   int grid[K_COUNT]{};
   int max_T = 1;
   ucac_batch_config cfg{64, 256, 0};
-  hipGraph_t graph = nullptr, graph_u = nullptr;
-  hipGraphExec_t exec = nullptr, exec_u = nullptr;
+  GraphSet graphs;
   std::vector<int> it0;
   std::string err;
 };
@@ -1346,10 +1351,7 @@ int batch_build(ucac_batch* b) {
     g.blk_first = g.blk_member + b->grid[k];
     g.blk_count = g.blk_first + n;
   }
-  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->exec_u) { (void)hipGraphExecDestroy(b->exec_u); b->exec_u = nullptr; }
-  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-  if (b->graph_u) { (void)hipGraphDestroy(b->graph_u); b->graph_u = nullptr; }
+  b->graphs.clear();
   const char* where = "";
   auto launch = [&](int k, hipStream_t s) {
     if (k == K_FRONT) {
@@ -1367,26 +1369,20 @@ int batch_build(ucac_batch* b) {
     }
     return hipGetLastError();
   };
-  for (int reps : {1, GRAPH_UNROLL}) {
+  for (int j = 0; j < N_GRAPHS; ++j) {
     (void)hipGetLastError();
     BHIP_OR(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
-    for (int r = 0; r < reps && le == hipSuccess; ++r) le = enqueue_chain(launch, b->st, &where);
-    hipGraph_t& gr = reps == 1 ? b->graph : b->graph_u;
-    const hipError_t ce = hipStreamEndCapture(b->st, &gr);
+    for (int r = 0; r < GRAPH_SIZES[j] && le == hipSuccess; ++r) le = enqueue_chain(launch, b->st, &where);
+    const hipError_t ce = hipStreamEndCapture(b->st, &b->graphs.g[j]);
     if (le != hipSuccess) return bfail(b, UCAC_E_DEVICE, "grouped launch of %s failed: %s", where, hipGetErrorString(le));
     if (ce != hipSuccess) return bfail(b, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-    BHIP_OR(b, hipGraphInstantiate(reps == 1 ? &b->exec : &b->exec_u, gr, nullptr, nullptr, 0));
+    BHIP_OR(b, hipGraphInstantiate(&b->graphs.x[j], b->graphs.g[j], nullptr, nullptr, 0));
   }
   return UCAC_OK;
 }
 
-hipError_t batch_launch_iterations(ucac_batch* b, int n) {
-  hipError_t e = hipSuccess;
-  for (; n >= GRAPH_UNROLL && e == hipSuccess; n -= GRAPH_UNROLL) e = hipGraphLaunch(b->exec_u, b->st);
-  for (; n > 0 && e == hipSuccess; --n) e = hipGraphLaunch(b->exec, b->st);
-  return e;
-}
+hipError_t batch_launch_iterations(ucac_batch* b, int n) { return b->graphs.launch(n, b->st); }
 
 int batch_set_ctl(ucac_batch* b, int stop_at_tol, double tol) {
   for (ucac_handle* h : b->m) {
@@ -1631,10 +1627,7 @@ void ucac_batch_destroy(ucac_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
   if (b->st) (void)hipStreamSynchronize(b->st);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->exec_u) (void)hipGraphExecDestroy(b->exec_u);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->graph_u) (void)hipGraphDestroy(b->graph_u);
+  b->graphs.clear();
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_members) (void)hipFree(b->d_members);
   if (b->st) (void)hipStreamDestroy(b->st);

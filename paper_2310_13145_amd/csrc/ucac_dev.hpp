@@ -21,8 +21,9 @@ enum { ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF, NACC };
 
 constexpr int BLOCK = 256;
 // Line-kernel work counters per wavefront: evaluations, rejected trials, CG
-// iterations, Newton iterations, learned-start fallbacks, direct Newton steps.
-constexpr int NBRC = 6;
+// iterations, Newton iterations, learned-start fallbacks, direct Newton steps,
+// projected searches.
+constexpr int NBRC = 7;
 // Block size of the generator and relaxed-commitment kernels: they have few items
 // (12,000 unit-periods at 2,000 buses), so smaller blocks spread the loads over more
 // CUs.  The others keep 256-thread blocks, which also keeps the number of residual
@@ -81,7 +82,7 @@ struct State {
   int* br_iters;                                               // [T][L]
   unsigned long long* br_count;  // [waves][NBRC] running totals per wavefront of the line kernel (global lane / 64):
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks,
-                                 // direct Newton steps
+                                 // direct Newton steps, projected searches
   double* red;                   // [red_n][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
   int red_units, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
   double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres

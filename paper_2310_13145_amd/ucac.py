@@ -281,10 +281,10 @@ def ucac_kernel_times(h, n_iters):
 
 
 def ucac_branch_counters(h, reset=False):
-    out = np.zeros(6, dtype=np.uint64)
+    out = np.zeros(7, dtype=np.uint64)
     _check(lib().ucac_branch_counters(h, _ptr(out), int(bool(reset))), h)
     return dict(evals=int(out[0]), rejected=int(out[1]), cg=int(out[2]), newton=int(out[3]), fallbacks=int(out[4]),
-                direct=int(out[5]))
+                direct=int(out[5]), searches=int(out[6]))
 
 
 MLP_PARAMS = 5764

@@ -266,9 +266,16 @@ def test_full_size_sampled():
     g.step(39)
     s = g.get_state()
     o.set_state(s)
+    g.branch_counters(reset=True)
     g.step(1)
     o.step(1)
     compare(g.get_state(), o.get_state(), inst, 1e-10, "cfg2 it41")
+    # the projected search (a step through a bound stopped at the first bound its ray
+    # reaches), the direct Newton step and CG all ran in this compared iteration (at
+    # the cold start every line solve is already converged at its start point)
+    cnt = g.branch_counters()
+    print(f"[parity] cfg2 it41 counters {cnt}", flush=True)
+    assert cnt["searches"] > 0 and cnt["direct"] > 0 and cnt["cg"] > 0
 
 
 def test_set_params_midway_matches_oracle():
