@@ -36,8 +36,10 @@ HBM_PEAK_GBS = 8000.0
 FLOP_EVAL = 349      # value + gradient + 10-entry Hessian at one point (inactive line limits)
 FLOP_TRIAL = 75      # value only at a trial point (what a rejected trial needs)
 FLOP_CG = 80         # one Steihaug-Toint CG iteration on the 4x4 system
-FLOP_DIRECT = 110    # one Newton step by the 4x4 LDL^T factorization (free-set assembly, 4 refined
-                     # reciprocals, elimination, triangular solves, length test)
+FLOP_DIRECT = 83     # one direct Newton step in its usual reduced form: the angle sum decouples, so a
+                     # 3x3 LDL^T (free-set assembly, 3 refined reciprocals, elimination, triangular
+                     # solves) plus one product for the sum, back to the angles, length test (the 4x4
+                     # form, 110, runs only with an angle on its +-2 pi bound and is counted as 83)
 FLOP_NEWTON = 80     # per trust-region iteration: projection, predicted reduction, ratio, radius
 FLOP_SEARCH = 64     # one projected search: four break points, the new trial point and step, and the
                      # model value at it (Hessian product, two dot products)

@@ -249,9 +249,36 @@ __device__ inline void steihaug(const Sym4& H, const double (&g)[4], const doubl
 // and CG returns it.  Returns true with that step in d; false (indefinite H_ff or a
 // step of length >= delta) leaves the step to CG.  The fixed variables get identity
 // rows, so their step is zero.  About 70 operations against about 120 per CG
-// iteration.
+// iteration for the 4x4 form; the usual reduced 3x3 form needs about 50.
 __device__ inline bool newton_step_direct(const Sym4& H, const double (&g)[4], const double (&fr)[4], double delta,
-                                          double (&d)[4]) {
+                                          double inv_rva, double (&d)[4]) {
+  if (fr[2] != 0.0 && fr[3] != 0.0) {
+    // Both angles free (their bounds are +-2 pi): in the coordinates D = th_i - th_j,
+    // S = th_i + th_j the flows depend on D alone, so S decouples (its curvature is
+    // rho_va / 2, its coupling to v_i, v_j and D is zero) and the system is 3x3 in
+    // (v_i, v_j, D): H_DD = (h22 - h23) / 2, H_vD = h02, h12, g_D = (g2 - g3) / 2.
+    const double a00 = fr[0] * H.h00 + (1.0 - fr[0]), a11 = fr[1] * H.h11 + (1.0 - fr[1]);
+    const double a01 = fr[0] * fr[1] * H.h01, a02 = fr[0] * H.h02, a12 = fr[1] * H.h12;
+    const double a22 = 0.5 * (H.h22 - H.h23);
+    const double d0 = a00, i0 = qrcp(d0);
+    const double l10 = a01 * i0, l20 = a02 * i0;
+    const double d1 = a11 - a01 * l10, i1 = qrcp(d1);
+    const double b12 = a12 - a02 * l10;
+    const double l21 = b12 * i1;
+    const double d2 = (a22 - a02 * l20) - b12 * l21;
+    const bool pd = d0 > 0.0 && d1 > 0.0 && d2 > 0.0;
+    const double i2 = qrcp(d2);
+    const double y0 = -fr[0] * g[0];
+    const double y1 = -fr[1] * g[1] - l10 * y0;
+    const double y2 = (-0.5 * (g[2] - g[3]) - l20 * y0) - l21 * y1;
+    const double sD = y2 * i2;
+    const double s1 = y1 * i1 - l21 * sD;
+    const double s0 = (y0 * i0 - l10 * s1) - l20 * sD;
+    const double sS = -(g[2] + g[3]) * inv_rva;  // -g_S / (rho_va / 2), g_S = (g2 + g3) / 2
+    const double s2 = 0.5 * (sS + sD), s3 = 0.5 * (sS - sD);
+    d[0] = s0; d[1] = s1; d[2] = s2; d[3] = s3;
+    return pd && (s0 * s0 + s1 * s1) + (s2 * s2 + s3 * s3) < delta * delta;
+  }
   const double a00 = fr[0] * H.h00 + (1.0 - fr[0]), a11 = fr[1] * H.h11 + (1.0 - fr[1]);
   const double a22 = fr[2] * H.h22 + (1.0 - fr[2]), a33 = fr[3] * H.h33() + (1.0 - fr[3]);
   const double a01 = fr[0] * fr[1] * H.h01, a02 = fr[0] * fr[2] * H.h02, a03 = fr[0] * fr[3] * H.h03();
@@ -344,6 +371,7 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
   for (int i = 0; i < 4; ++i) xe[i] = x[i];
   double F = 0.0, pred = 0.0, snorm = 0.0;
   double delta = 1.0;
+  const double inv_rva = 1.0 / L.rva;
   bool trial = false;
   conv = false;
   int it = 0;
@@ -384,7 +412,7 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
     }
     if (pg <= p.gtol) { conv = true; break; }
     double d[4];
-    if (newton_step_direct(H, g, fr, delta, d)) ++n_dir;
+    if (newton_step_direct(H, g, fr, delta, inv_rva, d)) ++n_dir;
     else steihaug(H, g, fr, nf, delta, d, n_cg);
     double sv[4];
     bool left_box = false;

@@ -44,6 +44,24 @@ def test_members_match_single_instances():
     b.close()
 
 
+def test_members_match_across_graph_sizes():
+    """85 batch iterations in one call (graphs of 64, 16, 4 and 1) against each member
+    run alone in single steps."""
+    insts = members()[:3]
+    ref = []
+    for inst in insts:
+        s = ucac.Solver(inst)
+        for _ in range(85):
+            s.step(1)
+        ref.append(s.get_state())
+        s.close()
+    b = ucac.Batch(insts)
+    b.step(85)
+    for k in range(len(insts)):
+        np.testing.assert_array_equal(b.member(k).get_state(), ref[k], err_msg=f"member {k}")
+    b.close()
+
+
 @pytest.mark.parametrize("cfg", ucac.BATCH_CANDIDATES)
 def test_every_mapping_bit_identical(cfg):
     insts = members()
