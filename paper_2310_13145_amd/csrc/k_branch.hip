@@ -23,6 +23,7 @@
 #include "ucac_launch.hpp"
 #include "ucac_mlp.hpp"
 #include "ucac_units.hpp"
+#include "ucac_ctl.hpp"
 
 namespace ucac {
 
@@ -628,11 +629,23 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) k_
 // the same iteration, and one launch on one stream avoids the fork and join that two
 // concurrent launches cost on the iteration's critical path.  The unit blocks come
 // first, so that they start with the first wave of line blocks.
+//
+// With fin_units >= 0 the first block is instead the control step of the previous
+// iteration (its unit side's residual slots from fin_units on).  Nothing else in this
+// launch reads what the control step writes, except the stop flag, which it sets only
+// in solve mode, where the step runs as a kernel of its own; the unit blocks write the
+// other copy of their slots (s.red_u).
 template <int START, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
-k_front(Net n, State s, Par p, int nb_units, int gpb) {
-  if ((int)blockIdx.x < nb_units) unit_body<BS>(n, s, p, blockIdx.x, n.T, gpb);
-  else branch_body<START, BS>(n, s, p, blockIdx.x - nb_units);
+k_front(Net n, State s, Par p, int nb_units, int gpb, int fin_units) {
+  static_assert(BS == FIN_BLOCK, "the control step runs as one block of this launch");
+  int b = blockIdx.x;
+  if (fin_units >= 0) {
+    if (b == 0) { finalize_body(s, p, fin_units); return; }
+    --b;
+  }
+  if (b < nb_units) unit_body<BS>(n, s, p, b, n.T, gpb);
+  else branch_body<START, BS>(n, s, p, b - nb_units);
 }
 
 template <int START, int BS>
@@ -711,21 +724,24 @@ void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t
 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_branch_block(n, s, p, st, 256); }
 
-void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st) {
+void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, int fin_units) {
   const int TL = n.T * n.L;
   const int gpb = units_gpb(n.T, 16, 256);
   const int nu = n.G && n.T ? units_blocks(n, gpb) : 0;
   const int nb = TL ? branch_blocks(n, 256) : 0;
-  if (nu + nb == 0) return;
+  const int nf = fin_units >= 0 ? 1 : 0;
+  if (nu + nb + nf == 0) return;
   if (TL && p.warm_start == START_LEARNED) {
     const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
     hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
   }
   const size_t lds = nu ? units_lds(n.T, gpb) : 0;
-  const dim3 grid(nu + nb), block(256);
-  if (p.warm_start == START_LEARNED) hipLaunchKernelGGL((k_front<START_LEARNED, 256>), grid, block, lds, st, n, s, p, nu, gpb);
-  else if (p.warm_start == START_PREV) hipLaunchKernelGGL((k_front<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb);
-  else hipLaunchKernelGGL((k_front<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb);
+  const dim3 grid(nf + nu + nb), block(256);
+  if (p.warm_start == START_LEARNED)
+    hipLaunchKernelGGL((k_front<START_LEARNED, 256>), grid, block, lds, st, n, s, p, nu, gpb, fin_units);
+  else if (p.warm_start == START_PREV)
+    hipLaunchKernelGGL((k_front<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb, fin_units);
+  else hipLaunchKernelGGL((k_front<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb, fin_units);
 }
 
 template <int BS>

@@ -6,12 +6,12 @@
 
 namespace ucac {
 
-__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(s, p); }
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Net n, State s, Par p) { finalize_body(s, p, s.red_u); }
 
 __global__ void __launch_bounds__(FIN_BLOCK) k_finalize_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
   const Member& M = gr.m[mk];
-  finalize_body(M.s, M.p);
+  finalize_body(M.s, M.p, M.s.red_u);
 }
 
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {

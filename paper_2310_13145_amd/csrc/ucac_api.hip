@@ -73,7 +73,8 @@ struct ucac_handle {
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;      // pinned staging of the control block
   double* h_sc = nullptr;    // pinned staging of the scalars
-  GraphSet graphs;  // the iteration captured GRAPH_SIZES[j] times back to back
+  GraphSet graphs;        // step mode: GRAPH_SIZES[j] iterations, control steps inside the next front launch
+  GraphSet graphs_solve;  // solve mode: GRAPH_SIZES[j] iterations, each with its own control-step kernel
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
@@ -219,7 +220,8 @@ size_t carve(ucac_handle* h, char* base) {
   s.red_bpost = s.red_bus + bus_blocks(n);
   s.red_gdual = s.red_bpost + line_blocks(n);
   s.red_n = s.red_gdual + gen_dual_blocks(n);
-  s.red = a.take<double>((size_t)s.red_n * NACC);
+  s.red_u = s.red_units;
+  s.red = a.take<double>((size_t)(s.red_n + n.G) * NACC);
   s.ebuf = a.take<double>(T * 2 * L * 4);
   s.bmu = a.take<double>(2 * T * N);
   s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
@@ -486,6 +488,31 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
   return enqueue_chain(launch, st, where);
 }
 
+// Iteration r of a step-mode graph of `size` iterations.  Its unit blocks write slot
+// copy r & 1; from the second iteration on, its front launch also runs the previous
+// iteration's control step (a block of its own, reading the other copy), which takes
+// that kernel off the critical path; the graph's last iteration ends with its own
+// control step.  Solve mode keeps the control step as a kernel after every iteration:
+// there it may stop the instance, and the next iteration must see that.
+hipError_t enqueue_step_iteration(ucac_handle* h, hipStream_t st, int r, int size, const char** where) {
+  State sr = h->st;
+  const int copy[2] = {h->st.red_units, h->st.red_n};
+  sr.red_u = copy[r & 1];
+  const int fin = r > 0 ? copy[(r - 1) & 1] : -1;
+  launch_front(h->net, sr, h->kp, st, fin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { if (where) *where = "front"; return e; }
+  launch_bus(h->net, h->st, h->kp, st);
+  if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "bus"; return e; }
+  launch_post(h->net, h->st, h->kp, st);
+  if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "post"; return e; }
+  if (r == size - 1) {
+    launch_finalize(h->net, sr, h->kp, st);
+    if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "finalize"; return e; }
+  }
+  return hipSuccess;
+}
+
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
   static const char* names[] = {"units", "branch", "bus", "post", "finalize"};
@@ -499,22 +526,31 @@ hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where,
 
 int build_graph(ucac_handle* h) {
   h->graphs.clear();
-  for (int j = 0; j < N_GRAPHS; ++j) {
-    (void)hipGetLastError();
-    HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
-    const char* where = "";
-    hipError_t le = hipSuccess;
-    for (int r = 0; r < GRAPH_SIZES[j] && le == hipSuccess; ++r) le = enqueue_iteration(h, h->own, &where);
-    const hipError_t ce = hipStreamEndCapture(h->own, &h->graphs.g[j]);
-    if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
-    if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-    HIP_OR(h, hipGraphInstantiate(&h->graphs.x[j], h->graphs.g[j], nullptr, nullptr, 0));
+  h->graphs_solve.clear();
+  for (int solve = 0; solve < 2; ++solve) {
+    GraphSet& gs = solve ? h->graphs_solve : h->graphs;
+    for (int j = 0; j < N_GRAPHS; ++j) {
+      (void)hipGetLastError();
+      HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
+      const char* where = "";
+      hipError_t le = hipSuccess;
+      const int size = GRAPH_SIZES[j];
+      for (int r = 0; r < size && le == hipSuccess; ++r)
+        le = solve ? enqueue_iteration(h, h->own, &where) : enqueue_step_iteration(h, h->own, r, size, &where);
+      const hipError_t ce = hipStreamEndCapture(h->own, &gs.g[j]);
+      if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
+      if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+      HIP_OR(h, hipGraphInstantiate(&gs.x[j], gs.g[j], nullptr, nullptr, 0));
+    }
   }
   return UCAC_OK;
 }
 
-// Enqueue n iterations, largest graph first.
-hipError_t launch_iterations(ucac_handle* h, int n) { return h->graphs.launch(n, h->stream); }
+// Enqueue n iterations, largest graph first (solve mode: with a control-step kernel
+// after every iteration).
+hipError_t launch_iterations(ucac_handle* h, int n, bool solve = false) {
+  return (solve ? h->graphs_solve : h->graphs).launch(n, h->stream);
+}
 
 // Write the host-owned control fields (never inside a captured graph).
 int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
@@ -667,7 +703,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
       hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * NBRC * branch_waves(h)) != hipSuccess ||
-      hipMemset(h->st.red, 0, sizeof(double) * NACC * h->st.red_n) != hipSuccess)
+      hipMemset(h->st.red, 0, sizeof(double) * NACC * (h->st.red_n + h->net.G)) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
   if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
@@ -720,7 +756,7 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
   bool done = false;
   while (!done && launched < max_iters) {
     const int k = (max_iters - launched) < SOLVE_CHUNK ? (max_iters - launched) : SOLVE_CHUNK;
-    HIP_OR(h, launch_iterations(h, k));
+    HIP_OR(h, launch_iterations(h, k, true));
     launched += k;
     rc = read_status(h);
     if (rc) return rc;
@@ -1258,6 +1294,7 @@ void ucac_destroy(ucac_handle* h) {
   (void)hipSetDevice(h->par.device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   h->graphs.clear();
+  h->graphs_solve.clear();
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);

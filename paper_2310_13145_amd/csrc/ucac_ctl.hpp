@@ -24,8 +24,10 @@ namespace ucac {
 constexpr int FIN_BLOCK = 256;  // largest block that runs the control step
 
 // The control step of one iteration, run by one whole block: reduce every per-block
-// residual slot of the iteration, advance the counters and decide (see above).
-__device__ inline void finalize_body(const State& s, const Par& p) {
+// residual slot of the iteration (the unit side's from slot units_slot on), advance the
+// counters and decide (see above).
+__device__ inline void finalize_body(const State& s, const Par& p, const int units_slot) {
+#pragma clang fp contract(off)
   Ctl* c = s.ctl;
   double* sc = s.sc;
   // The control fields and counters are loaded first (uniform addresses), so that
@@ -48,7 +50,10 @@ __device__ inline void finalize_body(const State& s, const Par& p) {
     for (int u = 0; u < U; ++u) {
       const int b = b0 + u * (int)blockDim.x;
 #pragma unroll
-      for (int k = 0; k < NACC; ++k) v[u][k] = b < s.red_n ? s.red[(size_t)b * NACC + k] : 0.0;
+      for (int k = 0; k < NACC; ++k) {
+        const int slot = b < s.red_bus ? units_slot + b : b;
+        v[u][k] = b < s.red_n ? s.red[(size_t)slot * NACC + k] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -85,6 +85,10 @@ struct State {
                                  // direct Newton steps, projected searches
   double* red;                   // [red_n][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
   int red_units, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
+  // The unit side's slots have a second copy at red_n (G slots), so that an iteration's
+  // control step can run beside the next iteration's unit blocks: red_u is where this
+  // launch's unit blocks write (red_units or red_n).
+  int red_u;
   double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres
   double* bmu;                   // [2][T][N] balance multipliers of the bus QP
   float* x0;                     // [4][T][L] start points of the learned Newton start (FP32)

@@ -28,8 +28,9 @@ int branch_blocks(const Net& n, int block);
 int bus_blocks(const Net& n);
 int post_blocks(const Net& n);
 int lambda_blocks(const Net& n);
-// the unit side and the lines in one launch: the units' blocks first, then the lines'
-void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st);
+// the unit side and the lines in one launch: the units' blocks first, then the lines';
+// with fin_units >= 0 a first block runs the previous iteration's control step
+void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, int fin_units = -1);
 void launch_front_grouped(const Group& gu, int grid_u, const Group& gb, int grid_b, int warm_start, int block,
                           int dp_lanes, int max_T, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);

@@ -331,7 +331,7 @@ __device__ __forceinline__ void unit_body(const Net& n, const State& s, const Pa
     for (int t = tb; t < T; t += TPAR) dmax = nmax(dmax, ubar_item(n, s, p, t * G + g));
   const double v[1] = {dmax};
   const int which[1] = {ACC_RD};
-  block_max_store<1>(v, which, s.red + (size_t)(s.red_units + blk) * NACC);
+  block_max_store<1>(v, which, s.red + (size_t)(s.red_u + blk) * NACC);
 }
 
 // Blocks for the unit side at gpb generators per block.
