@@ -104,9 +104,9 @@ def lib():
         L.orc_branch_eval.restype = C.c_double
         L.orc_branch_F.argtypes = [vp, vp]
         L.orc_branch_F.restype = C.c_double
-        L.orc_branch_solve.argtypes = [vp, vp, C.c_int, C.c_double, ip]
+        L.orc_branch_solve.argtypes = [vp, vp, C.c_int, C.c_double, C.c_int, ip]
         L.orc_branch_solve.restype = C.c_int
-        L.orc_branch_trial.argtypes = [vp, vp, C.c_double, vp]
+        L.orc_branch_trial.argtypes = [vp, vp, C.c_double, C.c_int, vp]
         L.orc_branch_trial.restype = C.c_double
         L.orc_line_admittance.argtypes = [C.c_double, C.c_double, C.c_double, vp]
         L.orc_line_flows.argtypes = [vp, vp, vp]
@@ -269,21 +269,23 @@ def branch_F(v, x):
     return lib().orc_branch_F(_ptr(v), _ptr(x))
 
 
-def branch_solve(v, x0, max_iter=50, gtol=1e-8):
+def branch_solve(v, x0, max_iter=50, gtol=1e-8, hold=False):
     v = np.ascontiguousarray(v, dtype=np.float64)
     x = np.array(x0, dtype=np.float64)
     cg = C.c_int32(0)
-    it = lib().orc_branch_solve(_ptr(v), _ptr(x), int(max_iter), float(gtol), C.byref(cg))
+    it = lib().orc_branch_solve(_ptr(v), _ptr(x), int(max_iter), float(gtol), int(bool(hold)), C.byref(cg))
     return x, it, cg.value
 
 
-def branch_trial(v, x, delta):
+def branch_trial(v, x, delta, hold=False):
     """Trial point of one projected trust-region Newton iteration from x (gradient,
-    Hessian and free set taken at x) and the model value q(xt - x)."""
+    Hessian and free set taken at x) and the model value q(xt - x); hold: the hold
+    step of warm starts (a free variable on a bound that the step pushes outwards is
+    held there and the step solved again)."""
     v = np.ascontiguousarray(v, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     xt = np.zeros(4)
-    q = lib().orc_branch_trial(_ptr(v), _ptr(x), float(delta), _ptr(xt))
+    q = lib().orc_branch_trial(_ptr(v), _ptr(x), float(delta), int(bool(hold)), _ptr(xt))
     return xt, q
 
 

@@ -298,12 +298,24 @@ static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v >
  * q(s) <= mu0 g.s with mu0 = 0.01, the step instead stops at the first break point
  * of the ray x + alpha d (the projected search of Lin and More's TRON, the solver
  * the paper hands the line subproblem to): the model decreases along the ray up to
- * there, and the variable whose bound is reached first is placed on it.  Writes the
- * trial point xt and step s = xt - x; returns the model value q(s). */
+ * there, and the variable whose bound is reached first is placed on it.  Before that,
+ * a free variable that lies on a bound but that the step pushes outwards is held on
+ * its bound and the step solved again without it.  Writes the trial point xt and step
+ * s = xt - x; returns the model value q(s). */
 static double trial_point(const branch_pb *b, const double *x, const double *g, double H[4][4], const int *fr,
-                          double delta, double *xt, double *s, int *cg_its) {
+                          double delta, int hold, double *xt, double *s, int *cg_its) {
   double d[4];
   steihaug(H, g, fr, delta, d, cg_its);
+  /* with hold set, a free variable on a bound (its gradient points inwards) that the
+   * step pushes outwards is held on it, and the step is solved once more without it:
+   * TRON's subspace step holds every variable that is on a bound */
+  int fr2[4], held = 0;
+  for (int i = 0; i < 4; ++i) {
+    int out = hold && fr[i] && ((x[i] <= b->lo[i] && d[i] < 0.0) || (x[i] >= b->hi[i] && d[i] > 0.0));
+    fr2[i] = out ? 0 : fr[i];
+    held |= out;
+  }
+  if (held) steihaug(H, g, fr2, delta, d, cg_its);
   int left_box = 0;
   for (int i = 0; i < 4; ++i) {
     double xd = x[i] + d[i];
@@ -348,7 +360,7 @@ static double trial_point(const branch_pb *b, const double *x, const double *g, 
 /* Projected trust-region Newton (Nocedal & Wright Alg. 4.1 with the trial point
  * above).  Returns the number of Newton iterations taken; x holds the start on entry
  * and the result on exit. */
-static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol, int *cg_total) {
+static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol, int hold, int *cg_total) {
   double g[4], H[4][4];
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], b->lo[i], b->hi[i]);
   double F = branch_eval(b, x, g, H);
@@ -366,7 +378,7 @@ static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol
     }
     if (pg <= gtol) break;
     double xt[4], s[4];
-    double q = trial_point(b, x, g, H, fr, delta, xt, s, &cg_its);
+    double q = trial_point(b, x, g, H, fr, delta, hold, xt, s, &cg_its);
     double sinf = 0.0, xinf = 0.0;
     for (int i = 0; i < 4; ++i) {
       if (fabs(s[i]) > sinf) sinf = fabs(s[i]);
@@ -925,7 +937,8 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
       } else {
         x[0] = 0.5 * (P->vmin[i] + P->vmax[i]); x[1] = 0.5 * (P->vmin[j] + P->vmax[j]); x[2] = 0.0; x[3] = 0.0;
       }
-      P->br_iters[k] = branch_solve(&b, x, P->par.newton_max_iter, gtol, NULL);
+      /* the hold step is taken from warm starts, whose lanes often begin on a bound */
+      P->br_iters[k] = branch_solve(&b, x, P->par.newton_max_iter, gtol, P->par.warm_start != 0, NULL);
       double f[4];
       line_flows(b.adm, x, f);
       S->vf[k] = x[0]; S->vt[k] = x[1]; S->thf[k] = x[2]; S->tht[k] = x[3];
@@ -1241,21 +1254,21 @@ double orc_branch_F(const double *v, const double *x) {
   return branch_F(&b, x);
 }
 
-int orc_branch_solve(const double *v, double *x, int max_iter, double gtol, int *cg_its) {
+int orc_branch_solve(const double *v, double *x, int max_iter, double gtol, int hold, int *cg_its) {
   branch_pb b;
   unpack_branch(v, &b);
-  return branch_solve(&b, x, max_iter, gtol, cg_its);
+  return branch_solve(&b, x, max_iter, gtol, hold, cg_its);
 }
 
 /* One trial point from x with radius delta (evaluates g and H at x itself). */
-double orc_branch_trial(const double *v, const double *x, double delta, double *xt) {
+double orc_branch_trial(const double *v, const double *x, double delta, int hold, double *xt) {
   branch_pb b;
   unpack_branch(v, &b);
   double g[4], H[4][4], s[4];
   int fr[4], cg = 0;
   branch_eval(&b, x, g, H);
   for (int i = 0; i < 4; ++i) fr[i] = !((x[i] <= b.lo[i] && g[i] > 0.0) || (x[i] >= b.hi[i] && g[i] < 0.0));
-  return trial_point(&b, x, g, H, fr, delta, xt, s, &cg);
+  return trial_point(&b, x, g, H, fr, delta, hold, xt, s, &cg);
 }
 
 void orc_line_admittance(double r, double x, double b, double *adm) { line_admittance(r, x, b, adm); }

@@ -222,6 +222,20 @@ def test_determinism_and_resume_bit_exact():
     np.testing.assert_array_equal(a.get_state(), c.get_state())
 
 
+@pytest.mark.parametrize("name", ["ring9_T6", "mesh118_T24", "mesh14_tight_limits"])
+def test_previous_iterate_start_matches_oracle(name):
+    """Line Newton started from the line's previous solution (warm_start = 1), with the
+    hold step of warm starts, against the oracle doing the same: one iteration, then 50."""
+    inst = INSTANCES[name]()
+    g, o = pair(inst, warm_start=1)
+    g.step(1)
+    o.step(1)
+    compare(g.get_state(), o.get_state(), inst, 1e-10, f"{name} prev it1")
+    g.step(49)
+    o.step(49)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, f"{name} prev it50")
+
+
 def test_graph_sizes_bit_exact():
     """ucac_step replays graphs of 64, 16, 4 and 1 iterations, largest first: 85
     iterations in one call (64 + 16 + 4 + 1), in single steps, and in uneven calls

@@ -116,7 +116,8 @@ def test_branch_solve_is_stationary_and_minimal():
         assert res.fun >= F - 1e-9 * max(1.0, abs(F))
 
 
-def test_branch_trial_projected_search():
+@pytest.mark.parametrize("hold", [False, True])
+def test_branch_trial_projected_search(hold):
     """One trial point of the line Newton where the free Hessian is positive definite
     and the Newton step lies inside the region (Steihaug's step is the Newton step
     there).  A step that stays in the box is taken whole.  One that leaves it is
@@ -126,10 +127,13 @@ def test_branch_trial_projected_search():
     with that variable exactly on its bound and, where the trial lies on the ray, the
     model strictly decreased.  The
     sample holds projections whose model value lies in (0.01 g.s, 0]: a decrease, but
-    too small, so they are searched.  (The variable that sets alpha is also placed on
+    too small, so they are searched, and free variables on a bound that the Newton step
+    pushes outwards: with the hold step (taken from warm starts) those are held on the
+    bound and the step solved without them (TRON's subspace step holds every variable
+    on a bound); without it they are projected like the others.  (The variable that sets alpha is also placed on
     its bound explicitly, a guard: x + alpha d lands on it exactly in every case seen.)"""
     rng = np.random.default_rng(11)
-    seen = {"inside": 0, "clip": 0, "search": 0, "small_decrease": 0}
+    seen = {"inside": 0, "clip": 0, "search": 0, "small_decrease": 0, "held": 0}
     for trial in range(8000):
         v, _ = random_branch(rng, rate=rng.choice([0.5, 2.5]))
         v[9:11] = 0.95
@@ -147,10 +151,21 @@ def test_branch_trial_projected_search():
         # three cases differ at the scale of the step)
         d = np.zeros(4)
         d[fr] = -np.linalg.solve(Hf, g[fr])
+        # a free variable on a bound that the step pushes outwards is held there and the
+        # step solved again without it
+        held = fr & (((x <= lo) & (d < 0)) | ((x >= hi) & (d > 0))) & hold
+        if held.any():
+            fr = fr & ~held
+            Hf = H[np.ix_(fr, fr)]
+            if np.linalg.eigvalsh(Hf).min() <= 0:
+                continue
+            d = np.zeros(4)
+            d[fr] = -np.linalg.solve(Hf, g[fr])
         delta = 10.0
         if np.linalg.norm(d) >= 0.5 * delta:
             continue
-        xt, q = oracle.branch_trial(v, x, delta)
+        seen["held"] += int(held.any())
+        xt, q = oracle.branch_trial(v, x, delta, hold)
         model = lambda st: g @ st + 0.5 * st @ H @ st
         xd = x + d
         if not np.any((xd < lo) | (xd > hi)):
@@ -180,6 +195,8 @@ def test_branch_trial_projected_search():
         # outwards its projection leaves the ray, and the ratio test decides as before
         if not np.any(((d > 0) & (x >= hi)) | ((d < 0) & (x <= lo))):
             assert model(xt - x) < 0.0
+    if not hold:
+        seen.pop("held")
     assert min(seen.values()) >= 3, seen
 
 
