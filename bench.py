@@ -309,7 +309,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the workload is one "
-              "instance on one MI355X; see DESIGN.md for how it would shard", file=sys.stderr)
+              "instance on one MI355X; multi-GPU execution is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

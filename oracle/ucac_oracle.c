@@ -20,7 +20,7 @@
  *   - outer update: step:outer with tau = 6, theta = 0.8, Alg. alg:basic;
  *   - UC block: the DP of Sec. III-B (keep_formula, switch_formula, Alg. dp_algo);
  *   - generator / bus / line blocks: the component-based decomposition the paper
- *     adopts from its ExaAdmm.jl lineage, with the readings listed in the design doc
+ *     adopts from its ExaAdmm.jl lineage, with the readings stated at each block
  *     (ramp rows on the bus-side duplicate of p_{t-1}, ramp-down row as in the
  *     inequality, line limits by a PHR term, projected trust-region Newton).
  *

@@ -183,13 +183,13 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double rpq = p.rho_pq, rva = p.rho_va;
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
-    // round 1
+    // first load round
     const int e0 = n.inc_start[i], e1 = n.inc_start[i + 1];
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
     const double wold = s.wb[idx], thold = s.thb[idx];
     const double gsh = n.gs[i], bsh = n.bs[i], Pd = n.Pd[idx], Qd = n.Qd[idx];
-    // round 2: the first unit's index; round 3: its data, issued before the end sums'
-    // loads (which need only round 1) so that those travel with them
+    // second load round: the first unit's index; third: its data, issued before the end
+    // sums' loads (which need only the first round) so that those travel with them
     const int nu = g1 - g0;
     UnitRaw u0raw;
     if (nu > 0) u0raw = unit_raw(n, s, t, n.gen_list[g0]);
