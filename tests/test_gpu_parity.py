@@ -309,6 +309,26 @@ def test_full_size_sampled():
     assert cnt["searches"] > 0 and cnt["direct"] > 0 and cnt["cg"] > 0
 
 
+def test_full_size_10000_buses():
+    """The 10,000-bus, T = 48 workload (624,000 line solves per iteration) in the same
+    launch configuration: one iteration from the cold start, then one from a GPU
+    iterate after 20 iterations, each against the oracle from the same state."""
+    inst = synth.config_instance(4)
+    g, o = pair(inst)
+    g.step(1)
+    o.step(1)
+    compare(g.get_state(), o.get_state(), inst, 1e-10, "cfg4 it1")
+    g.step(19)
+    o.set_state(g.get_state())
+    g.branch_counters(reset=True)
+    g.step(1)
+    o.step(1)
+    compare(g.get_state(), o.get_state(), inst, 1e-10, "cfg4 it21")
+    cnt = g.branch_counters()
+    print(f"[parity] cfg4 it21 counters {cnt}", flush=True)
+    assert cnt["searches"] > 0 and cnt["direct"] > 0
+
+
 def test_set_params_midway_matches_oracle():
     """Penalties changed on a live handle (the multipliers are unscaled, so the iterate
     carries over) give the oracle's trajectory under the same change."""
