@@ -700,10 +700,12 @@ __global__ void __launch_bounds__(BLOCK) k_line_start(Net n, State s, Par p) {
   const int TL = n.T * n.L;
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   const bool active = idx < TL;
+  MlpFrags fr;
+  mlp_load_frags(p.mlp, fr);  // in flight with the line's own loads
   const Line L = load_line(n, s, p, idx, active);
   float f[MLP_IN], y[MLP_OUT];
   line_features(L, f);
-  mlp_forward_wave(p.mlp, f, lds_start + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
+  mlp_forward_frags(fr, p.mlp.b3, f, lds_start + (threadIdx.x >> 6) * MLP_WAVE_LDS, y);
   if (active) {
     s.x0[idx] = 1.0f + y[0];
     s.x0[TL + idx] = 1.0f + y[1];

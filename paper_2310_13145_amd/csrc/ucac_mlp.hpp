@@ -43,14 +43,45 @@ __device__ inline int d_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3
 // error ~1e-6 before the result is rounded to BF16).
 __device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
+// A lane's operands of the three layers: its weight fragments (the A operands of its
+// MFMAs) and the biases of the outputs it finishes.  Loaded before any other work, so
+// that their latency overlaps the inputs' loads instead of following each layer's
+// barrier.
+struct MlpFrags {
+  bf16x8 a1[MLP_H / 32][MLP_KIN / 16], a2[MLP_H / 32][MLP_H / 16], a3[MLP_H / 16];
+  float b1[MLP_H / 32][4][4], b2[MLP_H / 32][4][4];
+};
+
+__device__ inline void mlp_load_frags(const Mlp& w, MlpFrags& f) {
+  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int to = 0; to < MLP_H / 32; ++to) {
+#pragma unroll
+    for (int ks = 0; ks < MLP_KIN / 16; ++ks) f.a1[to][ks] = ld8(w.W1b + (to * 32 + r) * MLP_KIN + ks * 16 + h * 8);
+#pragma unroll
+    for (int ks = 0; ks < MLP_H / 16; ++ks) f.a2[to][ks] = ld8(w.W2b + (to * 32 + r) * MLP_H + ks * 16 + h * 8);
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f.b1[to][jb][q] = w.b1[to * 32 + 8 * jb + 4 * h + q];
+        f.b2[to][jb][q] = w.b2[to * 32 + 8 * jb + 4 * h + q];
+      }
+  }
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks) f.a3[ks] = ld8(w.W3b + r * MLP_H + ks * 16 + h * 8);
+}
+
 // In place: X [64 samples][K] (LDS rows, stride MLP_LD) becomes
 // silu(X W^T + b) [64][NOUT], computed as the product W X^T so that the MFMA
 // result of a lane is four consecutive outputs of one sample (one 8-byte LDS
-// store): A = W rows (global), B = X rows (LDS), D[out][sample].  Each 32-sample
-// tile is read completely before it is overwritten; the block barriers order the
-// reads of every lane before the writes, so every lane of the block calls this.
+// store): A = W rows (this lane's fragments), B = X rows (LDS), D[out][sample].
+// Each 32-sample tile is read completely before it is overwritten; the block
+// barriers order the reads of every lane before the writes, so every lane of the
+// block calls this.
 template <int K, int NOUT>
-__device__ inline void layer_silu_inplace(__bf16* X, const __bf16* W, const float* bias) {
+__device__ inline void layer_silu_inplace(__bf16* X, const bf16x8 (&A)[NOUT / 32][K / 16],
+                                          const float (&bias)[NOUT / 32][4][4]) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int ts = 0; ts < 2; ++ts) {  // sample tile
@@ -59,8 +90,7 @@ __device__ inline void layer_silu_inplace(__bf16* X, const __bf16* W, const floa
     for (int to = 0; to < NOUT / 32; ++to) {
       acc[to] = f32x16{};
 #pragma unroll
-      for (int ks = 0; ks < K / 16; ++ks)
-        acc[to] = mfma(ld8(W + (to * 32 + r) * K + ks * 16 + h * 8), ld8(X + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[to]);
+      for (int ks = 0; ks < K / 16; ++ks) acc[to] = mfma(A[to][ks], ld8(X + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[to]);
     }
     __syncthreads();
     __bf16* row = X + (ts * 32 + r) * MLP_LD;
@@ -72,17 +102,19 @@ __device__ inline void layer_silu_inplace(__bf16* X, const __bf16* W, const floa
         typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
         bf16x4 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (__bf16)silu_fast(acc[to][4 * jb + q] + bias[o + q]);
+        for (int q = 0; q < 4; ++q) v[q] = (__bf16)silu_fast(acc[to][4 * jb + q] + bias[to][jb][q]);
         *reinterpret_cast<bf16x4*>(row + o) = v;
       }
     __syncthreads();
   }
 }
 
-// Forward pass of the 64 samples of one wavefront.  feat: this lane's 20 inputs;
-// buf: MLP_WAVE_LDS BF16 of LDS private to the wavefront.  Every lane of the
-// block must call this (block barriers inside).  out: this lane's 4 outputs.
-__device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN], __bf16* buf, float (&out)[MLP_OUT]) {
+// Forward pass of the 64 samples of one wavefront with the operands in fr.  feat:
+// this lane's 20 inputs; buf: MLP_WAVE_LDS BF16 of LDS private to the wavefront.
+// Every lane of the block must call this (block barriers inside).  out: this lane's
+// 4 outputs.
+__device__ inline void mlp_forward_frags(const MlpFrags& fr, const float* b3, const float (&feat)[MLP_IN], __bf16* buf,
+                                         float (&out)[MLP_OUT]) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -96,8 +128,8 @@ __device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN
     }
   }
   __syncthreads();
-  layer_silu_inplace<MLP_KIN, MLP_H>(buf, w.W1b, w.b1);
-  layer_silu_inplace<MLP_H, MLP_H>(buf, w.W2b, w.b2);
+  layer_silu_inplace<MLP_KIN, MLP_H>(buf, fr.a1, fr.b1);
+  layer_silu_inplace<MLP_H, MLP_H>(buf, fr.a2, fr.b2);
   // output layer, W3 padded to 32 rows: outputs 0..3 of sample ts*32 + r sit in
   // acc[0..3] of lane r (h = 0)
   f32x16 acc[2];
@@ -105,8 +137,7 @@ __device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN
   for (int ts = 0; ts < 2; ++ts) {
     acc[ts] = f32x16{};
 #pragma unroll
-    for (int ks = 0; ks < MLP_H / 16; ++ks)
-      acc[ts] = mfma(ld8(w.W3b + r * MLP_H + ks * 16 + h * 8), ld8(buf + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[ts]);
+    for (int ks = 0; ks < MLP_H / 16; ++ks) acc[ts] = mfma(fr.a3[ks], ld8(buf + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[ts]);
   }
   __syncthreads();
   float* Yf = reinterpret_cast<float*>(buf);  // [64][4] FP32 over the consumed activations
@@ -114,12 +145,18 @@ __device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN
 #pragma unroll
     for (int ts = 0; ts < 2; ++ts)
 #pragma unroll
-      for (int o = 0; o < MLP_OUT; ++o) Yf[(ts * 32 + r) * MLP_OUT + o] = acc[ts][o] + w.b3[o];
+      for (int o = 0; o < MLP_OUT; ++o) Yf[(ts * 32 + r) * MLP_OUT + o] = acc[ts][o] + b3[o];
   }
   __syncthreads();
 #pragma unroll
   for (int o = 0; o < MLP_OUT; ++o) out[o] = Yf[lane * MLP_OUT + o];
   __syncthreads();
+}
+
+__device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN], __bf16* buf, float (&out)[MLP_OUT]) {
+  MlpFrags fr;
+  mlp_load_frags(w, fr);
+  mlp_forward_frags(fr, w.b3, feat, buf, out);
 }
 
 }  // namespace ucac
