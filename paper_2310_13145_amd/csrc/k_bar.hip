@@ -165,10 +165,10 @@ __device__ inline UnitPre unit_pre(const UnitRaw& r, const Par& p, int t, int T)
   return u;
 }
 
-// One lane per (bus, t).  The loads form three dependent rounds: (1) the bus's own
-// values and its incidence ranges; (2) the first unit's index; (3) that unit's terms,
-// rows and previous values (kept in registers through the solve and the update)
-// together with the sums of up to eight line ends.  The end loads are
+// One lane per (bus, t).  The loads form two dependent rounds: (1) the bus's own
+// values, its incidence ranges and its first unit (a static per-bus index); (2) that
+// unit's terms, rows and previous values (kept in registers through the solve and the
+// update) together with the sums of up to eight line ends.  The end loads are
 // unconditional (clamped indices; the contributions of unused slots are selected away
 // as +0.0, which leaves every sum exactly as if they were skipped), so that none of
 // them waits behind another; the sums keep the incidence order.
@@ -188,11 +188,12 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const int g0 = n.gen_start[i], g1 = n.gen_start[i + 1];
     const double wold = s.wb[idx], thold = s.thb[idx];
     const double gsh = n.gs[i], bsh = n.bs[i], Pd = n.Pd[idx], Qd = n.Qd[idx];
-    // second load round: the first unit's index; third: its data, issued before the end
-    // sums' loads (which need only the first round) so that those travel with them
+    const int gfirst = n.unit_first[i];
+    // second load round: the first unit's data, issued before the end sums' loads so
+    // that both travel together
     const int nu = g1 - g0;
     UnitRaw u0raw;
-    if (nu > 0) u0raw = unit_raw(n, s, t, n.gen_list[g0]);
+    if (nu > 0) u0raw = unit_raw(n, s, t, gfirst);
     double Ww = 0.0, Sw = 0.0, Wt = 0.0, St = 0.0;
     double M11 = 0.0, M12 = 0.0, M22 = 0.0, aT = 0.0, bT = 0.0;
     const double* eb = s.ebuf + (size_t)t * 2 * n.L * 4;

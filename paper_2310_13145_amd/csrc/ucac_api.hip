@@ -204,7 +204,7 @@ size_t carve(ucac_handle* h, char* base) {
   n.gs = a.take<double>(N); n.bs = a.take<double>(N); n.vmin = a.take<double>(N); n.vmax = a.take<double>(N);
   n.Pd = a.take<double>(T * N); n.Qd = a.take<double>(T * N);
   n.inc_start = a.take<int>(N + 1); n.inc_code = a.take<int>(2 * L); n.end_pos = a.take<int>(2 * L);
-  n.gen_start = a.take<int>(N + 1); n.gen_list = a.take<int>(G);
+  n.gen_start = a.take<int>(N + 1); n.gen_list = a.take<int>(G); n.unit_first = a.take<int>(N);
   n.pmin = a.take<double>(G); n.pmax = a.take<double>(G); n.qmin = a.take<double>(G); n.qmax = a.take<double>(G);
   n.k2 = a.take<double>(G); n.k1 = a.take<double>(G); n.cnl = a.take<double>(G); n.csu = a.take<double>(G);
   n.csd = a.take<double>(G); n.ru = a.take<double>(G); n.rd = a.take<double>(G); n.su = a.take<double>(G);
@@ -645,6 +645,9 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
     std::vector<int> fill(N, 0);
     for (size_t g = 0; g < G; ++g) gen_list[gen_start[net->gen_bus[g]] + fill[net->gen_bus[g]]++] = (int)g;
   }
+  std::vector<int> unit_first(N, 0);
+  for (size_t i = 0; i < N; ++i)
+    if (gen_start[i + 1] > gen_start[i]) unit_first[i] = gen_list[gen_start[i]];
   const double base = net->base_mva;
   h->hg.k2.resize(G); h->hg.k1.resize(G);
   for (size_t g = 0; g < G; ++g) { h->hg.k2[g] = net->gen_c2[g] * base * base; h->hg.k1[g] = net->gen_c1[g] * base; }
@@ -685,6 +688,7 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
       {(void*)n.inc_start, inc_start.data(), sizeof(int) * (N + 1)}, {(void*)n.inc_code, inc_code.data(), sizeof(int) * 2 * L},
       {(void*)n.end_pos, end_pos.data(), sizeof(int) * 2 * L},
       {(void*)n.gen_start, gen_start.data(), sizeof(int) * (N + 1)}, {(void*)n.gen_list, gen_list.data(), sizeof(int) * G},
+      {(void*)n.unit_first, unit_first.data(), sizeof(int) * N},
       {(void*)n.pmin, net->gen_pmin, sizeof(double) * G}, {(void*)n.pmax, net->gen_pmax, sizeof(double) * G},
       {(void*)n.qmin, net->gen_qmin, sizeof(double) * G}, {(void*)n.qmax, net->gen_qmax, sizeof(double) * G},
       {(void*)n.k2, h->hg.k2.data(), sizeof(double) * G}, {(void*)n.k1, h->hg.k1.data(), sizeof(double) * G},

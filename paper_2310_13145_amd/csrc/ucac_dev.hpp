@@ -59,6 +59,7 @@ struct Net {
   const int* end_pos;    // [2L] position of line end line*2 + side in the incidence list
   const int* gen_start;  // [N+1]
   const int* gen_list;   // [G]
+  const int* unit_first;  // [N] gen_list[gen_start[i]], the bus's first unit (0 for a bus without one)
   // generators [G]
   const double *pmin, *pmax, *qmin, *qmax, *k2, *k1, *cnl, *csu, *csd, *ru, *rd, *su, *sd, *p0;
   const int *tu, *td, *u0, *lon, *loff;
