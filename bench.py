@@ -68,7 +68,7 @@ BYTES_BUS_POST = 8 * 64     # per (line, t), both ends: flows, targets, bus resu
 # plain copy kernel of known size.  They describe the kernel source they were taken
 # on (hash below) and are reported as null once that source has changed.
 BRANCH_COUNTERS = {"source_sha256": "7364cbdab6e2bfdee55cb095a02e0bf185714bd2a0fc8bb9387370f73b041919",
-                   "fetch_kib": 8058.5, "write_kib": 11203.5, "fetch_scale": 2.0, "write_scale": 1.0}
+                   "fetch_kib": 8047.7, "write_kib": 11184.3, "fetch_scale": 2.0, "write_scale": 1.0}
 BRANCH_SOURCES = ("k_branch.hip", "ucac_mlp.hpp")  # the line kernel's own code
 
 
