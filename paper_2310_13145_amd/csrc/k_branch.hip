@@ -694,11 +694,15 @@ k_front_group(Group gu, Group gb, int grid_u, int slotT, int gpb) {
 // (v_i, v_j, th_i, th_j) as FP32 in x0 [4][T*L].  A kernel of its own so that the
 // Newton kernel keeps its registers (no spills) and the network runs at the
 // occupancy its small footprint allows.
-__global__ void __launch_bounds__(BLOCK) k_line_start(Net n, State s, Par p) {
+// One wavefront per block: the forward pass's block barriers then wait for no other
+// wavefront, and the launch spreads over every CU.
+constexpr int START_BLOCK = 64;
+
+__global__ void __launch_bounds__(START_BLOCK) k_line_start(Net n, State s, Par p) {
   if (s.ctl->halt) return;
   extern __shared__ __bf16 lds_start[];
   const int TL = n.T * n.L;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  const int idx = blockIdx.x * START_BLOCK + threadIdx.x;
   const bool active = idx < TL;
   MlpFrags fr;
   mlp_load_frags(p.mlp, fr);  // in flight with the line's own loads
@@ -716,6 +720,11 @@ __global__ void __launch_bounds__(BLOCK) k_line_start(Net n, State s, Par p) {
 
 int branch_blocks(const Net& n, int block) { return (n.T * n.L + block - 1) / block; }
 
+static void launch_line_start(const Net& n, const State& s, const Par& p, hipStream_t st) {
+  const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (START_BLOCK / 64);
+  hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, START_BLOCK)), dim3(START_BLOCK), lds, st, n, s, p);
+}
+
 // With e0 set, the launch carries its own start and stop events, which take the
 // dispatch's begin and end timestamps: the kernel's duration without the latency
 // of separate event records around it.
@@ -732,10 +741,7 @@ static void launch_branch_bs(const Net& n, const State& s, const Par& p, int gri
 static void launch_branch_impl(const Net& n, const State& s, const Par& p, hipStream_t st, int block, hipEvent_t e0,
                                hipEvent_t e1) {
   if (n.T * n.L == 0) return;
-  if (p.warm_start == START_LEARNED) {
-    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
-    hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
-  }
+  if (p.warm_start == START_LEARNED) launch_line_start(n, s, p, st);
   const int grid = branch_blocks(n, block);
   if (block == 64) launch_branch_bs<64>(n, s, p, grid, p.warm_start, st, e0, e1);
   else launch_branch_bs<256>(n, s, p, grid, p.warm_start, st, e0, e1);
@@ -758,10 +764,7 @@ void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, in
   const int nb = TL ? branch_blocks(n, 256) : 0;
   const int nf = fin_units >= 0 ? 1 : 0;
   if (nu + nb + nf == 0) return;
-  if (TL && p.warm_start == START_LEARNED) {
-    const size_t lds = sizeof(__bf16) * MLP_WAVE_LDS * (BLOCK / 64);
-    hipLaunchKernelGGL(k_line_start, dim3(branch_blocks(n, BLOCK)), dim3(BLOCK), lds, st, n, s, p);
-  }
+  if (TL && p.warm_start == START_LEARNED) launch_line_start(n, s, p, st);
   const size_t lds = nu ? units_lds(n.T, gpb) : 0;
   const dim3 grid(nf + nu + nb), block(256);
   if (p.warm_start == START_LEARNED)
