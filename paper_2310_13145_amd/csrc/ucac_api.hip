@@ -79,6 +79,8 @@ struct ucac_handle {
   HostGen hg;
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
+  // ucac_solve's snapshot at the start of each chunk: state, control block, work counters
+  void* solve_save = nullptr;
   // locality ordering: internal index -> caller's index
   std::vector<int> perm_bus, perm_line, perm_gen;
   std::string err;
@@ -492,8 +494,9 @@ hipError_t enqueue_iteration(ucac_handle* h, hipStream_t st, const char** where)
 // copy r & 1; from the second iteration on, its front launch also runs the previous
 // iteration's control step (a block of its own, reading the other copy), which takes
 // that kernel off the critical path; the graph's last iteration ends with its own
-// control step.  Solve mode keeps the control step as a kernel after every iteration:
-// there it may stop the instance, and the next iteration must see that.
+// control step.  Such a step cannot stop an instance (the next front launch already
+// runs beside it); ucac_solve runs these graphs from a snapshot and replays the last
+// chunk, ending in one solve-mode iteration, to stop at the right iteration.
 hipError_t enqueue_step_iteration(ucac_handle* h, hipStream_t st, int r, int size, const char** where) {
   State sr = h->st;
   const int copy[2] = {h->st.red_units, h->st.red_n};
@@ -559,6 +562,7 @@ int set_ctl(ucac_handle* h, int stop_at_tol, double tol) {
   h->h_ctl->tol = tol;
   const double ms[3] = {1e-2, 1e-3, 1e-4};
   for (int m = 0; m < 3; ++m) { h->h_ctl->ms_tol[m] = ms[m]; h->h_ctl->ms_iter[m] = -1; }
+  h->h_ctl->conv_iter = -1;
   HIP_OR(h, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   return UCAC_OK;
 }
@@ -754,18 +758,58 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
   // clear the converged flag of a previous solve
   h->h_sc[SC_CONV] = 0.0;
   HIP_OR(h, hipMemcpyAsync(h->st.sc + SC_CONV, h->h_sc + SC_CONV, sizeof(double), hipMemcpyHostToDevice, h->stream));
-  rc = set_ctl(h, 1, tol);
+  // The chunks run in step mode (each control step inside the next launch), which
+  // cannot stop an instance; the control step records the first iteration at the
+  // tolerance instead.  When a chunk reaches it, the chunk is replayed from its
+  // snapshot up to the iteration before, and that iteration runs in solve mode, whose
+  // control step stops the instance there: the same iterations and state as solve
+  // mode throughout (the two forms compute the same iteration bit for bit).
+  rc = set_ctl(h, 0, tol);
   if (rc) return rc;
+  const size_t state_bytes = sizeof(double) * h->n_state;
+  const size_t count_bytes = sizeof(unsigned long long) * NBRC * branch_waves(h);
+  if (!h->solve_save && hipMalloc(&h->solve_save, state_bytes + sizeof(Ctl) + count_bytes) != hipSuccess) {
+    h->solve_save = nullptr;
+    return fail(h, UCAC_E_NOMEM, "solve snapshot allocation failed");
+  }
+  char* save = (char*)h->solve_save;
+  auto snapshot = [&](bool restore) -> hipError_t {
+    void* s0 = save;
+    void* s1 = save + state_bytes;
+    void* s2 = save + state_bytes + sizeof(Ctl);
+    hipError_t e = hipMemcpyAsync(restore ? (void*)h->d_state : s0, restore ? s0 : (void*)h->d_state, state_bytes,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(restore ? (void*)h->d_ctl : s1, restore ? s1 : (void*)h->d_ctl, sizeof(Ctl),
+                         hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess && count_bytes)
+      e = hipMemcpyAsync(restore ? (void*)h->st.br_count : s2, restore ? s2 : (void*)h->st.br_count, count_bytes,
+                         hipMemcpyDeviceToDevice, h->stream);
+    return e;
+  };
   int launched = 0;
   bool done = false;
   while (!done && launched < max_iters) {
     const int k = (max_iters - launched) < SOLVE_CHUNK ? (max_iters - launched) : SOLVE_CHUNK;
-    HIP_OR(h, launch_iterations(h, k, true));
-    launched += k;
+    HIP_OR(h, snapshot(false));
+    HIP_OR(h, launch_iterations(h, k));
     rc = read_status(h);
     if (rc) return rc;
     if (h->h_ctl->bad) break;
-    done = h->h_sc[SC_CONV] != 0.0;
+    if (h->h_ctl->conv_iter > 0) {
+      const int j = h->h_ctl->conv_iter - launched;  // the chunk's iteration at the tolerance, from 1
+      HIP_OR(h, snapshot(true));
+      HIP_OR(h, launch_iterations(h, j - 1));
+      h->h_ctl->stop_at_tol = 1;  // pinned staging
+      HIP_OR(h, hipMemcpyAsync(&h->d_ctl->stop_at_tol, &h->h_ctl->stop_at_tol, sizeof(int), hipMemcpyHostToDevice,
+                               h->stream));
+      HIP_OR(h, launch_iterations(h, 1, true));
+      rc = read_status(h);
+      if (rc) return rc;
+      done = true;
+      break;
+    }
+    launched += k;
   }
   rc = read_status(h);
   if (rc) return rc;
@@ -1305,6 +1349,7 @@ void ucac_destroy(ucac_handle* h) {
   if (h->h_sc) (void)hipHostFree(h->h_sc);
   if (h->arena) (void)hipFree(h->arena);
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
+  if (h->solve_save) (void)hipFree(h->solve_save);
   delete h;
 }
 
@@ -1432,6 +1477,7 @@ int batch_set_ctl(ucac_batch* b, int stop_at_tol, double tol) {
     h->h_ctl->tol = tol;
     const double ms[3] = {1e-2, 1e-3, 1e-4};
     for (int q = 0; q < 3; ++q) { h->h_ctl->ms_tol[q] = ms[q]; h->h_ctl->ms_iter[q] = -1; }
+    h->h_ctl->conv_iter = -1;
     BHIP_OR(b, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, b->st));
   }
   return UCAC_OK;

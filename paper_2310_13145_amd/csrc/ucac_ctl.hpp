@@ -33,7 +33,7 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
   // The control fields and counters are loaded first (uniform addresses), so that
   // their latency overlaps the slot loads; a halted instance is checked only
   // before the stores (the reduction itself only reads).
-  const int halt = c->halt, stop = c->stop_at_tol, ms_count = c->ms_count;
+  const int halt = c->halt, stop = c->stop_at_tol, ms_count = c->ms_count, conv_iter = c->conv_iter;
   const double tol = c->tol;
   int ms_iter[3];
   double ms_tol[3];
@@ -85,6 +85,7 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
   c->ms_count = ms_count + 1;
   for (int k = 0; k < 3; ++k)
     if (ms_iter[k] < 0 && rp <= ms_tol[k] && rd <= ms_tol[k]) c->ms_iter[k] = ms_count + 1;
+  if (conv_iter < 0 && rp <= tol && rd <= tol) c->conv_iter = ms_count + 1;
   if (stop && rp <= tol && rd <= tol) {
     sc[SC_LIN] = lin + 1.0;
     sc[SC_CONV] = 1.0;

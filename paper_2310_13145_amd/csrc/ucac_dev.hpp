@@ -43,6 +43,7 @@ struct Ctl {
   double ms_tol[3];              // residual milestones 1e-2, 1e-3, 1e-4 of a solve
   int ms_iter[3];                // first iteration (counted from the solve start) with r_p, r_d <= ms_tol; -1 if not yet
   int ms_count;                  // iterations since the solve started
+  int conv_iter;                 // first iteration (counted like ms_iter) with r_p, r_d <= tol; -1 if not yet
 };
 
 struct Net {
