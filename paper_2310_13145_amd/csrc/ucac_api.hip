@@ -20,8 +20,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Poll the device-side status every this many iterations in ucac_solve; the
-// next chunk is already queued while the host reads the previous one.
+// ucac_solve examines the device-side status after every chunk of this many
+// iterations.  (Queuing the next chunk before examining the previous one, with two
+// snapshots, measured no faster: the host turnaround is not what solve mode pays.)
 constexpr int SOLVE_CHUNK = 32;
 
 // Iterations are captured in graphs of 64, 16, 4 and 1 iterations, and n
