@@ -171,6 +171,30 @@ def test_solve_ring9_matches_oracle():
     np.testing.assert_array_equal(sol["u_on"].ravel(), S["uon"].astype(np.int8))
 
 
+def test_solve_stops_mid_chunk_without_trace():
+    """A solve runs its iterations in chunks from a snapshot and replays the chunk that
+    reaches the tolerance: its result (iterations, line-solve work counters, every state
+    array but the control scalars the stopping iteration sets) is that of stepping the
+    same number of iterations, as if nothing after the stop had run."""
+    inst = synth.config_instance(1)
+    a = ucac.Solver(inst)
+    a.branch_counters(reset=True)
+    rc, n = a.solve(1e-2, 5000)
+    assert rc == 0 and n % 32 != 0  # stopped inside a chunk
+    ca = a.branch_counters()
+    b = ucac.Solver(inst)
+    b.branch_counters(reset=True)
+    b.step(n)
+    cb = b.branch_counters()
+    assert ca == cb, (ca, cb)
+    sa = ucac.split_state(a.get_state(), *dims(inst))
+    sb = ucac.split_state(b.get_state(), *dims(inst))
+    for name, _ in ucac.state_layout(*dims(inst)):
+        if name == "scalars" or name.startswith(("lB", "lG")):
+            continue  # the stopping iteration's control step differs: no outer update in a solve
+        np.testing.assert_array_equal(sa[name], sb[name], err_msg=name)
+
+
 def test_edge_cases():
     """T = 1; a single bus with no lines; units starting off with holds."""
     inst = synth.small_instance(9, 12, 3, 1, seed=21)
