@@ -485,6 +485,18 @@ def test_bus_block_with_shunts_and_ramp_rows():
     test_bus_block_kkt((inst, o.params, S0, S1))
 
 
+def test_ubar_block_kkt_with_start_ups():
+    """Relaxed-commitment KKT where units start up in the horizon (u_su = 1 at the
+    first period of the units that begin off), so the U2 rows of t + 1 matter."""
+    inst = synth.small_instance(14, 20, 5, 5, seed=81)
+    inst["gen_u0"] = np.array([0, 1, 1, 0, 1], np.int32)
+    o = oracle.Oracle(inst)
+    o.step(20)
+    S0 = o.state(); o.step(1); S1 = o.state()
+    assert S1["usu"].max() == 1.0
+    test_ubar_block_kkt((inst, o.params, S0, S1))
+
+
 def test_line_limits_active():
     """Tight ratings make the PHR term active; the line block stays stationary and
     nu follows nu <- max(0, nu + mu h) at each end."""

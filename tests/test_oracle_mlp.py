@@ -45,6 +45,29 @@ def test_adam_step():
     np.testing.assert_allclose(w1, w - 1e-2 * np.sign(g), rtol=1e-6)
 
 
+def test_adam_later_steps_closed_form():
+    """Adam (Kingma and Ba, Alg. 1; beta1 = 0.9, beta2 = 0.999) on the gradient sequence
+    g, 0, 0: after the first step the bias-corrected moments are geometric averages in
+    closed form, m_hat_t = b1^(t-1) (1 - b1) / (1 - b1^t) g and
+    v_hat_t = b2^(t-1) (1 - b2) / (1 - b2^t) g^2, so step t moves the weight by
+    lr m_hat_t / (sqrt(v_hat_t) + eps).  With g = 1 the step factors are
+    0.9/1.9 / sqrt(0.999/1.999) at t = 2 and 0.81/2.71 / sqrt(0.998001/2.997001) at t = 3
+    (the two betas in swapped roles would give 0.7261 and 0.7779)."""
+    lr, eps = 1e-2, 1e-8
+    g = np.array([1.0, -4.0])
+    w = np.array([0.3, 0.7])
+    m = np.zeros(2); v = np.zeros(2)
+    w1, m, v = mlp.adam(w, g, m, v, 1, lr)
+    w2, m, v = mlp.adam(w1, np.zeros(2), m, v, 2, lr)
+    w3, m, v = mlp.adam(w2, np.zeros(2), m, v, 3, lr)
+    f2 = (0.9 / 1.9) / (np.sqrt(0.999 / 1.999) + eps)
+    f3 = (0.81 / 2.71) / (np.sqrt(0.998001 / 2.997001) + eps)
+    np.testing.assert_allclose(w1 - w, -lr * np.sign(g), rtol=1e-7)
+    np.testing.assert_allclose(w2 - w1, -lr * np.sign(g) * np.array([f2, (0.9 / 1.9) / (np.sqrt(0.999 / 1.999) + eps / 4)]), rtol=1e-9)
+    np.testing.assert_allclose(w3 - w2, -lr * np.sign(g) * np.array([f3, (0.81 / 2.71) / (np.sqrt(0.998001 / 2.997001) + eps / 4)]), rtol=1e-9)
+    assert abs(f2 - 0.6700) < 1e-3 and abs(f3 - 0.5180) < 1e-3
+
+
 def test_training_lowers_loss():
     rng = np.random.default_rng(5)
     X = rng.normal(size=(512, mlp.N_IN))
