@@ -564,60 +564,77 @@ static double uc_cost(double cnl, double csu, double csd, double rho, int sp, in
   return L;
 }
 
-/* Alg. dp_algo.  Ltab[(t*2 + sp)*2 + s], t = 0..T-1.  The initial condition is
- * read as: hold u0 for the first L_g (u0 = 1) or F_g (u0 = 0) periods, then
- * continue from the DP value at the next period.  A switch near the end of the
- * horizon holds the new state only up to T (windows of set:UC end at T).
+/* The UC subproblem of one generator (Sec. III-B) as a memoized recursion.
+ * c(t, s) is the least cost of periods t..T when the state before period t is s.
+ * It is the smaller of the two choices the paper defines, keep_formula (stay in s
+ * for period t, then c(t+1, s)) and switch_formula (enter 1-s at t and hold it for
+ * T^min periods, T^U when switching on and T^D when switching off, then
+ * c(t + T^min, 1-s)); stay is taken on a tie.  The switch cost is summed left to
+ * right from L(t, s, 1-s), with the continuation added last.  c is zero beyond the
+ * horizon, so a switch near the end holds the new state only up to T (the windows
+ * of set:UC end at T).  Each evaluated (t, s) also keeps its optimal trajectory
+ * u_{t,s,t..T}, built from its successor's as the paper's u formulas state.
+ * Ltab[(t*2 + sp)*2 + s], t = 0..T-1, is L^UC_t(sp, s). */
+typedef struct {
+  int T, TU, TD;
+  const double *Ltab;
+  double *c;           /* [(T + 2) * 2], index t*2 + s */
+  unsigned char *done; /* whether c(t, s) has been evaluated */
+  int8_t *traj;        /* [(T + 2) * 2][T]: u_{t,s,t'} at traj[(t*2 + s)*T + t' - 1] */
+} uc_memo;
+
+static double uc_L(const uc_memo *m, int t, int sp, int s) { return m->Ltab[((size_t)(t - 1) * 2 + sp) * 2 + s]; }
+static int8_t *uc_traj(const uc_memo *m, int t, int s) { return m->traj + ((size_t)t * 2 + s) * m->T; }
+
+static double uc_cost_to_go(uc_memo *m, int t, int s) {
+  if (t > m->T) return 0.0;
+  if (m->done[t * 2 + s]) return m->c[t * 2 + s];
+  const int T = m->T, alt = 1 - s;
+  const int hold = alt ? m->TU : m->TD;
+  /* keep_formula */
+  double c_stay = uc_L(m, t, s, s) + uc_cost_to_go(m, t + 1, s);
+  /* switch_formula */
+  double c_switch = uc_L(m, t, s, alt);
+  int until = t + hold - 1 < T ? t + hold - 1 : T;
+  for (int tp = t + 1; tp <= until; ++tp) c_switch += uc_L(m, tp, alt, alt);
+  c_switch += uc_cost_to_go(m, t + hold, alt);
+  int8_t *u = uc_traj(m, t, s);
+  if (c_stay <= c_switch) {
+    m->c[t * 2 + s] = c_stay;
+    u[t - 1] = (int8_t)s;
+    if (t + 1 <= T) memcpy(u + t, uc_traj(m, t + 1, s) + t, (size_t)(T - t));
+  } else {
+    m->c[t * 2 + s] = c_switch;
+    for (int tp = t; tp <= until; ++tp) u[tp - 1] = (int8_t)alt;
+    if (t + hold <= T) memcpy(u + t + hold - 1, uc_traj(m, t + hold, alt) + t + hold - 1, (size_t)(T - t - hold + 1));
+  }
+  m->done[t * 2 + s] = 1;
+  return m->c[t * 2 + s];
+}
+
+/* Optimal schedule from the initial condition: a unit that starts in state u0 and
+ * must keep it for its first L_g (u0 = 1) or F_g (u0 = 0) periods pays those periods
+ * in state u0 and continues from c(hold + 1, u0) (the reading of the initial
+ * condition of Alg. dp_algo: the hold, not T^U / T^D, bounds the forced periods).
  * Writes u_on[0..T-1]; returns the optimal cost. */
 static double dp_solve(int T, const double *Ltab, int u0, int Lg, int Fg, int TU, int TD, int8_t *uon) {
-  double *c = (double *)calloc((size_t)(T + 2) * 2, sizeof(double)); /* c[(t)*2+s], t = 1..T+1 */
-  unsigned char *dec = (unsigned char *)calloc((size_t)(T + 2) * 2, 1);
-#define LT(t, sp, s) Ltab[((size_t)((t) - 1) * 2 + (sp)) * 2 + (s)]
+  uc_memo m = {T, TU, TD, Ltab, NULL, NULL, NULL};
+  m.c = (double *)calloc((size_t)(T + 2) * 2, sizeof(double));
+  m.done = (unsigned char *)calloc((size_t)(T + 2) * 2, 1);
+  m.traj = (int8_t *)calloc((size_t)(T + 2) * 2 * (size_t)(T > 0 ? T : 1), 1);
   int hold = u0 ? Lg : Fg;
   if (hold > T) hold = T;
   if (hold < 0) hold = 0;
-  for (int t = T; t >= 1; --t) {
-    if (t <= hold) break;
-    for (int s = 0; s < 2; ++s) {
-      double stay = LT(t, s, s) + c[(t + 1) * 2 + s];
-      int ns = 1 - s;
-      int Tm = ns ? TU : TD;
-      double sw = LT(t, s, ns);
-      int last = t + Tm - 1;
-      if (last > T) last = T;
-      for (int tp = t + 1; tp <= last; ++tp) sw += LT(tp, ns, ns);
-      int nxt = t + Tm;
-      sw += (nxt <= T) ? c[nxt * 2 + ns] : 0.0;
-      if (stay <= sw) { c[t * 2 + s] = stay; dec[t * 2 + s] = 0; }
-      else            { c[t * 2 + s] = sw;   dec[t * 2 + s] = 1; }
-    }
+  double cost = 0.0;
+  for (int t = 1; t <= hold; ++t) {
+    cost += uc_L(&m, t, u0, u0);
+    uon[t - 1] = (int8_t)u0;
   }
-  double cost;
-  int t = 1, s = u0;
-  if (hold > 0) {
-    cost = 0.0;
-    for (int k = 1; k <= hold; ++k) cost += LT(k, u0, u0);
-    cost += c[(hold + 1) * 2 + u0];
-    for (int k = 1; k <= hold; ++k) uon[k - 1] = (int8_t)u0;
-    t = hold + 1;
-  } else {
-    cost = c[1 * 2 + u0];
-  }
-  while (t <= T) {
-    if (dec[t * 2 + s] == 0) {
-      uon[t - 1] = (int8_t)s;
-      ++t;
-    } else {
-      int ns = 1 - s;
-      int Tm = ns ? TU : TD;
-      for (int k = t; k <= t + Tm - 1 && k <= T; ++k) uon[k - 1] = (int8_t)ns;
-      t += Tm;
-      s = ns;
-    }
-  }
-#undef LT
-  free(c);
-  free(dec);
+  cost += uc_cost_to_go(&m, hold + 1, u0);
+  if (hold < T) memcpy(uon + hold, uc_traj(&m, hold + 1, u0) + hold, (size_t)(T - hold));
+  free(m.c);
+  free(m.done);
+  free(m.traj);
   return cost;
 }
 
@@ -937,8 +954,8 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
       } else {
         x[0] = 0.5 * (P->vmin[i] + P->vmax[i]); x[1] = 0.5 * (P->vmin[j] + P->vmax[j]); x[2] = 0.0; x[3] = 0.0;
       }
-      /* the hold step is taken from warm starts, whose lanes often begin on a bound */
-      P->br_iters[k] = branch_solve(&b, x, P->par.newton_max_iter, gtol, P->par.warm_start != 0, NULL);
+      /* with the hold step of TRON's subspace step, from every start */
+      P->br_iters[k] = branch_solve(&b, x, P->par.newton_max_iter, gtol, 1, NULL);
       double f[4];
       line_flows(b.adm, x, f);
       S->vf[k] = x[0]; S->vt[k] = x[1]; S->thf[k] = x[2]; S->tht[k] = x[3];

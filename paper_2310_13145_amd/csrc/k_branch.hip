@@ -353,18 +353,17 @@ __device__ inline void projected_search(const double (&x)[4], const double (&d)[
   }
 }
 
-// Projected trust-region Newton from x (in place).  HOLD adds the hold step of warm
-// starts (below): their lanes often begin on a voltage bound, where the step can push
-// a variable whose gradient points inwards out of the box; from the flat start such
-// holds are rare (under 0.1 % of lanes) and the extra code costs the launch about
-// 10 %.  Returns the iterations taken;
+// Projected trust-region Newton from x (in place), with the hold step (below) from
+// every start: lanes that begin on a voltage bound (warm starts often do) would
+// otherwise be pushed out of the box by steps whose projection the ratio test then
+// rejects.  Returns the iterations taken;
 // conv is set when it stopped at the projected-gradient tolerance.  There is one
 // evaluation site: value, gradient and Hessian are formed at every trial point in
 // one pass (nearly every trial is accepted); after a rejection the gradient and
 // Hessian at x come back from LDS.  The ratio tests compare the actual decrease
 // with multiples of the predicted one (pred > 0), which decides as the quotient
 // does without a division on the dependency chain.
-template <int BS, bool HOLD>
+template <int BS>
 __device__ inline int newton(const Line& L, const double (&lo)[4], const double (&hi)[4], double (&x)[4], const Par& p,
                              const GHSave<BS>& save, int& n_eval, int& n_rej, int& n_cg, int& n_dir, int& n_srch,
                              bool& conv) {
@@ -416,29 +415,27 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
       pg = out ? pg : fmax(pg, fabs(g[i]));
     }
     if (pg <= p.gtol) { conv = true; break; }
+    // The step on the free set; then the hold step: a free variable on a bound (its
+    // gradient points inwards) that the step pushes outwards is held on it and the
+    // step solved once more without it, as TRON's subspace step holds every variable
+    // that is on a bound.  One call site for the two passes keeps the code (and the
+    // register allocation) of a single step solve.
     double d[4];
-    if (newton_step_direct(H, g, fr, delta, inv_rva, d)) ++n_dir;
-    else steihaug(H, g, fr, nf, delta, d, n_cg);
-    // HOLD (warm starts): a free variable on a bound (its gradient points inwards) that
-    // the step pushes outwards is held on it and the step solved once more without it,
-    // as TRON's subspace step holds every variable on a bound.
-    bool held = false;
-    if constexpr (HOLD) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        held = held || (fr[i] != 0.0 && ((x[i] <= lo[i] && d[i] < 0.0) || (x[i] >= hi[i] && d[i] > 0.0)));
-    }
-    if (held) {
-      double fs[4];
-      int nfs = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool out = fr[i] != 0.0 && ((x[i] <= lo[i] && d[i] < 0.0) || (x[i] >= hi[i] && d[i] > 0.0));
-        fs[i] = out ? 0.0 : fr[i];
-        nfs += fs[i] != 0.0 ? 1 : 0;
-      }
+    double fs[4] = {fr[0], fr[1], fr[2], fr[3]};
+    int nfs = nf;
+    for (int pass = 0;; ++pass) {
       if (newton_step_direct(H, g, fs, delta, inv_rva, d)) ++n_dir;
       else steihaug(H, g, fs, nfs, delta, d, n_cg);
+      if (pass) break;
+      bool held = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool out = fs[i] != 0.0 && ((x[i] <= lo[i] && d[i] < 0.0) || (x[i] >= hi[i] && d[i] > 0.0));
+        fs[i] = out ? 0.0 : fs[i];
+        nfs -= out ? 1 : 0;
+        held = held || out;
+      }
+      if (!held) break;
     }
     double sv[4];
     bool left_box = false;
@@ -572,11 +569,11 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   if (active) {
     bool conv;
-    it = newton<BS, (START != START_FLAT)>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
+    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
     if (START == START_LEARNED && !conv) {
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton<BS, (START != START_FLAT)>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
+      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
     }
     // z, y of the eight rows for the per-end sums below, loaded before this lane's
     // first store so that their latency overlaps the final flows

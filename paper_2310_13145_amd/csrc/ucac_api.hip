@@ -796,9 +796,12 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
     HIP_OR(h, launch_iterations(h, k));
     rc = read_status(h);
     if (rc) return rc;
-    if (h->h_ctl->bad) break;
-    if (h->h_ctl->conv_iter > 0) {
-      const int j = h->h_ctl->conv_iter - launched;  // the chunk's iteration at the tolerance, from 1
+    // The tolerance is examined before the non-finite flag: a chunk that reached the
+    // tolerance and went non-finite only after it is replayed up to the stopping
+    // iteration, so the iterations after it never count.
+    const int conv_iter = h->h_ctl->conv_iter;
+    if (conv_iter > 0) {
+      const int j = conv_iter - launched;  // the chunk's iteration at the tolerance, from 1
       HIP_OR(h, snapshot(true));
       HIP_OR(h, launch_iterations(h, j - 1));
       h->h_ctl->stop_at_tol = 1;  // pinned staging
@@ -807,9 +810,15 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
       HIP_OR(h, launch_iterations(h, 1, true));
       rc = read_status(h);
       if (rc) return rc;
+      // the replay computes the chunk's iterations again bit for bit, so its stopping
+      // iteration must stop the instance at the recorded iteration
+      if (h->h_sc[SC_CONV] == 0.0 || h->h_ctl->conv_iter != conv_iter)
+        return fail(h, UCAC_E_DEVICE, "solve replay diverged: the tolerance was recorded at iteration %d of the solve, "
+                    "the replay stopped at %d (converged flag %g)", conv_iter, h->h_ctl->conv_iter, h->h_sc[SC_CONV]);
       done = true;
       break;
     }
+    if (h->h_ctl->bad) break;
     launched += k;
   }
   rc = read_status(h);

@@ -195,6 +195,38 @@ def test_solve_stops_mid_chunk_without_trace():
         np.testing.assert_array_equal(sa[name], sb[name], err_msg=name)
 
 
+@pytest.mark.parametrize("edge", [1, 0])
+def test_solve_stops_at_chunk_edges(edge):
+    """A solve whose tolerance is first met at the first (edge = 1) or the last
+    (edge = 0) iteration of one of its 32-iteration chunks: the tolerance is chosen
+    from a stepped run's residuals as a strict running minimum at such an iteration.
+    The solve stops exactly there, and its iterate is that of stepping as far."""
+    inst = synth.config_instance(1)
+    a = ucac.Solver(inst)
+    worst = []
+    for _ in range(700):
+        a.step(1)
+        rp, rd, _, _ = a.residuals()
+        worst.append(max(rp, rd))
+    worst = np.array(worst)
+    cand = [n for n in range(33, len(worst) + 1)
+            if n % 32 == edge and worst[n - 1] < worst[:n - 1].min()]
+    assert cand, "no running minimum at a chunk edge"
+    n = cand[-1]
+    print(f"[parity] chunk-edge solve stops at iteration {n} (tol {worst[n - 1]:.6e})", flush=True)
+    b = ucac.Solver(inst)
+    rc, it = b.solve(float(worst[n - 1]), 5000)
+    assert rc == 0 and it == n
+    c = ucac.Solver(inst)
+    c.step(n)
+    sb = ucac.split_state(b.get_state(), *dims(inst))
+    sc = ucac.split_state(c.get_state(), *dims(inst))
+    for name, _ in ucac.state_layout(*dims(inst)):
+        if name == "scalars" or name.startswith(("lB", "lG")):
+            continue
+        np.testing.assert_array_equal(sb[name], sc[name], err_msg=name)
+
+
 def test_edge_cases():
     """T = 1; a single bus with no lines; units starting off with holds."""
     inst = synth.small_instance(9, 12, 3, 1, seed=21)

@@ -61,9 +61,12 @@ MUTATIONS = [
     ("y_update_without_z", "S->yB[r][k] += rho * (a[r] + z);", "S->yB[r][k] += rho * a[r];", 0,
      [f"{BLK}::test_z_and_y_updates"]),
     # the UC dynamic program (Alg. dp_algo)
-    ("dp_tie_switches", "if (stay <= sw)", "if (stay < sw)", 0, [f"{DPT}::test_ties_stay"]),
-    ("dp_window_too_long", "int last = t + Tm - 1;", "int last = t + Tm;", 0, [f"{DPT}::test_dp_matches_brute_force"]),
-    ("dp_min_up_down_swapped", "int Tm = ns ? TU : TD;", "int Tm = ns ? TD : TU;", 0, [f"{DPT}::test_dp_matches_brute_force"]),
+    ("dp_tie_switches", "if (c_stay <= c_switch)", "if (c_stay < c_switch)", 0, [f"{DPT}::test_ties_stay"]),
+    ("dp_window_too_long", "int until = t + hold - 1 < T ? t + hold - 1 : T;", "int until = t + hold < T ? t + hold : T;", 0,
+     [f"{DPT}::test_dp_matches_brute_force"]),
+    ("dp_min_up_down_swapped", "const int hold = alt ? m->TU : m->TD;", "const int hold = alt ? m->TD : m->TU;", 0,
+     [f"{DPT}::test_dp_matches_brute_force"]),
+    ("dp_initial_hold_ignored", "int hold = u0 ? Lg : Fg;", "int hold = 0;", 0, [f"{DPT}::test_dp_matches_brute_force"]),
     ("uc_cost_su_sd_swapped", "u[1] = (s - sp) > 0 ? (s - sp) : 0;", "u[1] = (sp - s) > 0 ? (sp - s) : 0;", 0,
      [f"{DPT}::test_uc_cost_terms", f"{DPT}::test_su_sd_reduction_exact"]),
     ("uc_cost_half_rho_dropped", "L += y[k] * r + 0.5 * rho * r * r;", "L += y[k] * r + rho * r * r;", 0,
