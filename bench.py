@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-tolerance runs")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iters", type=int, default=20000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start evaluation")
     ap.add_argument("--train-instances", type=int, default=2)
     ap.add_argument("--log-iters", type=int, default=300)
@@ -112,20 +112,48 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(inst, seconds):
-    """The FP64 oracle as it stands, single-threaded, on the same workload; a bounded
-    sample of iterations from the cold start."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(inst, seconds, state0=None):
+    """The FP64 oracle as it stands on the host: its parallel loops on every thread
+    OpenMP gives it (the host's share of cores) and on one thread, each for about
+    `seconds` of inner iterations of the same workload from the iterate the GPU's
+    timed region starts from (cold start if none)."""
     import oracle
-    o = oracle.Oracle(inst)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        o.step(1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or n >= 200:
-            break
-    res = dict(value=n / el, unit="iters/s", cores=1, kind="oracle",
-               sample=f"first {n} inner iterations from the cold start of the same workload, {el:.1f} s, one thread")
+    legs = {}
+    for label, n_thr in (("all_cores", 0), ("one_core", 1)):
+        oracle.set_threads(n_thr)
+        threads = oracle.max_threads()
+        o = oracle.Oracle(inst)
+        if state0 is not None:
+            o.set_state(state0)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds or n >= 400:
+                break
+        legs[label] = {"value": n / el, "threads": threads, "iters": n, "seconds": el}
+        del o
+    oracle.set_threads(0)
+    a = legs["all_cores"]
+    res = dict(value=a["value"], unit="iters/s", cores=a["threads"], kind="oracle",
+               sample=f"{a['iters']} inner iterations of the same workload from the iterate the timed region starts "
+                      f"from, {a['seconds']:.1f} s on {a['threads']} threads (OpenMP parallel for over each block's "
+                      f"items); the same on one thread: {legs['one_core']['value']:.2f} iters/s",
+               one_core=legs["one_core"], nproc=os.cpu_count(),
+               affinity=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+               cpu_model=_cpu_model())
     # the oracle's DP alone on the tables of the standalone DP benchmark (200 units per shape)
     dp = {}
     for G, T in DP_SHAPES:
@@ -134,7 +162,7 @@ def cpu_baseline(inst, seconds):
         t0 = time.perf_counter()
         for g in range(k):
             oracle.dp(tab[g], u0[g], lon[g], loff[g], tu[g], td[g])
-        dp[f"G{G}_T{T}"] = {"dp_per_s": k / (time.perf_counter() - t0), "sample": f"{k} units"}
+        dp[f"G{G}_T{T}"] = {"dp_per_s": k / (time.perf_counter() - t0), "sample": f"{k} units, one thread"}
     res["dp"] = dp
     return res
 
@@ -410,7 +438,7 @@ def main():
         out["learned_start"] = learned_start(ucac, synth, torch, args)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds, state0)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
         if "dp_standalone" in out:
             for k, v in out["dp_standalone"].items():

@@ -4,9 +4,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library behind
 ``include/ucac.h``) never calls it and shares no code with it.
 
-The C source (``ucac_oracle.c``) is plain, single-threaded FP64 code that
-follows the paper's formulation and iteration order; this module only marshals
-arguments through ctypes.
+The C source (``ucac_oracle.c``) is plain FP64 code that follows the paper's
+formulation and iteration order (an OpenMP parallel for over the independent
+items of each block, with results that do not depend on the thread count); this
+module only marshals arguments through ctypes.
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ SCALARS = ["beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r
 
 def build(verbose=False):
     """Compile the oracle with plain IEEE FP64 semantics (no contraction)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-Wall", "-o", _LIB, _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
@@ -110,12 +111,25 @@ def lib():
         L.orc_branch_trial.restype = C.c_double
         L.orc_line_admittance.argtypes = [C.c_double, C.c_double, C.c_double, vp]
         L.orc_line_flows.argtypes = [vp, vp, vp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
 
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (0: the OpenMP default)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def default_params(**over):

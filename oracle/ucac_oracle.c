@@ -8,8 +8,12 @@
  * table or helper with the HIP library; the only thing both sides consume is
  * the seeded instance data.
  *
- * It is plain and slow on purpose: single-threaded, every block written out in
- * the order the paper states it, with no blocking, fusion or reordering.
+ * It is plain and slow on purpose: every block written out in the order the paper
+ * states it, with no blocking, fusion or reordering.  The items of a block are
+ * independent (that is the decomposition of Sec. III), so each block's loop over
+ * them is an OpenMP parallel for; every item is computed by the same code whatever
+ * thread runs it, and the only reductions are maxima, which are exact, so the
+ * results do not depend on the thread count.
  *
  * What each part follows:
  *   - rows, costs and the augmented Lagrangian: Sec. II (eq:uc-acopf, eq:acopf,
@@ -29,6 +33,7 @@
  * residuals at convergence).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -872,8 +877,11 @@ static xbar_view old_view(const orc_problem *P) {
 static void block_uc(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
-  double *Lt = (double *)malloc(sizeof(double) * 4 * T);
-  int8_t *u = (int8_t *)malloc((size_t)T);
+#pragma omp parallel
+  {
+  double *Lt = (double *)malloc(sizeof(double) * 4 * (T > 0 ? T : 1));
+  int8_t *u = (int8_t *)malloc((size_t)(T > 0 ? T : 1));
+#pragma omp for schedule(static)
   for (int g = 0; g < G; ++g) {
     for (int t = 0; t < T; ++t) {
       size_t k = (size_t)t * G + g;
@@ -895,6 +903,7 @@ static void block_uc(orc_problem *P, const xbar_view *X) {
   }
   free(Lt);
   free(u);
+  }
 }
 
 static void gen_data_of(const orc_problem *P, int g, gen_data *d) {
@@ -909,6 +918,7 @@ static void gen_data_of(const orc_problem *P, int g, gen_data *d) {
 static void block_gen(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
     for (int g = 0; g < G; ++g) {
       size_t k = (size_t)t * G + g;
@@ -930,6 +940,7 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, L = P->L, N = P->N;
   double gtol = P->par.newton_gtol * fmax(1.0, fmax(P->par.rho_pq, P->par.rho_va));
+#pragma omp parallel for collapse(2) schedule(dynamic, 64)
   for (int t = 0; t < T; ++t) {
     for (int l = 0; l < L; ++l) {
       size_t k = (size_t)t * L + l;
@@ -974,6 +985,7 @@ static void block_ubar(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
   double ruc = P->par.rho_uc, rc = P->par.rho_cpl;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
     for (int g = 0; g < G; ++g) {
       size_t k = (size_t)t * G + g;
@@ -1018,6 +1030,7 @@ static void block_bus(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, L = P->L, N = P->N, G = P->G;
   double rpq = P->par.rho_pq, rva = P->par.rho_va, rc = P->par.rho_cpl;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
     for (int i = 0; i < N; ++i) {
       size_t bi = (size_t)t * N + i;
@@ -1102,6 +1115,9 @@ static void block_duals(orc_problem *P) {
   int T = P->T, L = P->L, G = P->G;
   double beta = S->sc[SC_BETA];
   double rp = 0.0, rin = 0.0, zinf = 0.0;
+  /* the line rows and the generator-side rows are two independent sets of items;
+   * the residual maxima are exact whatever the order */
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf)
   for (int t = 0; t < T; ++t) {
     for (int l = 0; l < L; ++l) {
       size_t k = (size_t)t * L + l;
@@ -1115,6 +1131,9 @@ static void block_duals(orc_problem *P) {
         rp = fmax(rp, fabs(a[r])); rin = fmax(rin, fabs(a[r] + z)); zinf = fmax(zinf, fabs(z));
       }
     }
+  }
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf)
+  for (int t = 0; t < T; ++t) {
     for (int g = 0; g < G; ++g) {
       size_t k = (size_t)t * G + g;
       double a[NRG];
@@ -1167,6 +1186,7 @@ static int iterate(orc_problem *P, int stop_at_tol) {
   /* dual residual: largest change of any duplicate */
   double rd = 0.0;
   size_t nx = xbar_count(P);
+#pragma omp parallel for schedule(static) reduction(max : rd)
   for (size_t k = 0; k < nx; ++k) rd = fmax(rd, fabs(S->wb[k] - P->xb_old[k]));
   S->sc[SC_RD] = rd;
   block_duals(P);        /* step:z, step:y */
@@ -1205,6 +1225,10 @@ void orc_set_params(orc_problem *P, const orc_params *par) { P->par = *par; }
 void orc_get_branch_iters(const orc_problem *P, int32_t *out) {
   for (size_t k = 0; k < (size_t)P->T * P->L; ++k) out[k] = P->br_iters[k];
 }
+
+/* threads of the parallel loops (0: the OpenMP default) and the default itself */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 double orc_objective(const orc_problem *P) {
   const orc_state *S = &P->st;

@@ -125,8 +125,8 @@ def _run_case(case, tmpdir):
     with open(csrc, "w") as f:
         f.write(src)
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-                           "-o", lib, csrc, "-lm"])
-    env = dict(os.environ, UCAC_ORACLE_LIB=lib)
+                           "-fopenmp", "-o", lib, csrc, "-lm"])
+    env = dict(os.environ, UCAC_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"] + targets,
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-400:]

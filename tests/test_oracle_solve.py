@@ -113,3 +113,19 @@ def test_deterministic_and_resume_bit_exact():
     c = oracle.Oracle(inst)
     c.step(65)
     np.testing.assert_array_equal(a.get_state(), c.get_state())
+
+
+def test_thread_count_invariance():
+    """The oracle's parallel loops give the same iterate bit for bit on one thread and
+    on every host thread (the items of each block are independent; the residuals are
+    maxima)."""
+    inst = synth.small_instance(30, 45, 8, 12, seed=33)
+    states = []
+    for n in (1, max(2, oracle.max_threads()), 3):
+        oracle.set_threads(n)
+        o = oracle.Oracle(inst)
+        o.step(60)
+        states.append(o.get_state())
+    oracle.set_threads(0)
+    for s in states[1:]:
+        np.testing.assert_array_equal(states[0], s)
