@@ -109,7 +109,24 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-dp", action="store_true", help="skip the standalone DP benchmark")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--hbm-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (reads and writes exactly 1 GiB per "
+                         "dispatch), the known-size kernel the HBM byte counters are scaled by")
     return ap.parse_args()
+
+
+def hbm_calibration(nbytes=1 << 30, reps=5):
+    """A multiply-by-one over 1 GiB of FP32: each dispatch reads and writes exactly nbytes.
+    Profiled with --pmc FETCH_SIZE (then WRITE_SIZE), it gives the ratio of true to counted
+    bytes that the line kernel's counters are scaled by."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    return {"read_bytes_per_dispatch": 4 * n, "write_bytes_per_dispatch": 4 * n, "dispatches": reps}
 
 
 def _cpu_model():
@@ -339,6 +356,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the workload is one "
               "instance on one MI355X; multi-GPU execution is not built", file=sys.stderr)
         sys.exit(2)
+    if args.hbm_calibration:
+        print(json.dumps(hbm_calibration()), flush=True)
+        return
 
     import torch
     from paper_2310_13145_amd import synth, ucac
