@@ -5,8 +5,9 @@ MI355X, FP64), plain flat-start Newton vs previous-iterate warm start.
 A "step" is one inner ADMM iteration over every component and period (UC DP,
 generator and line subproblems, relaxed commitments, bus projection, multiplier
 and residual updates, inner/outer control).  `value` = steps/s of the captured
-iteration graph with the instance resident in HBM.  A second pass of the same
-number of iterations launches the kernels one by one with HIP events on the
+iteration graph with the instance resident in HBM.  A second pass, from the
+iterate after 200 iterations and after one untimed launch of every kernel, runs
+100 iterations with the kernels launched one by one and HIP events on the
 library's stream; it gives each kernel's mean device time.  The line kernel of
 that pass also carries its own start/stop events (the dispatch's begin and end
 timestamps, what a kernel trace reports); its roofline fraction uses that
@@ -45,6 +46,11 @@ FLOP_SEARCH = 64     # one projected search: four break points, the new trial po
                      # model value at it (Hessian product, two dot products)
 FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, final flows, nu update,
                      # the bus QP's per-end sums
+
+# The profiled (kernel-by-kernel) pass starts from the iterate after PROF_FROM iterations and
+# times PROF_ITERS iterations, whatever --steps and --warmup are.
+PROF_FROM = 200
+PROF_ITERS = 100
 
 # Algorithmic HBM bytes per item, counted from the kernels' loads and stores (8 B per
 # double, each state array touched once per item; per-line/per-unit constants omitted):
@@ -387,11 +393,18 @@ def main():
     dt_warm = time.perf_counter() - t0
     warm.close()
 
-    # profiled pass: the iterations of the timed region again (same starting state, so the
-    # same Newton work), kernel by kernel with HIP events on the library's stream
+    # profiled pass, independent of --steps/--warmup: from the iterate after
+    # PROF_FROM iterations (past the cold-start transient), one untimed kernel-by-kernel
+    # iteration (every kernel's first launch in the process), then PROF_ITERS iterations
+    # kernel by kernel with HIP events on the library's stream; the line kernel's mean is
+    # taken from its dispatch timestamps, what a kernel trace of the same run reports
     solver.set_state(state0)
+    solver.step(max(0, PROF_FROM - args.warmup))
+    state_prof = solver.get_state()
+    solver.kernel_times(1)
+    solver.set_state(state_prof)
     solver.branch_counters(reset=True)
-    ktimes = solver.kernel_times(args.steps)
+    ktimes = solver.kernel_times(PROF_ITERS)
     cnt = solver.branch_counters(reset=True)
     branch_dispatch_ms = ktimes.pop("branch_dispatch")
     prof_ms_per_step = sum(ktimes.values())
@@ -402,7 +415,7 @@ def main():
     full = cnt["evals"] - cnt["rejected"]
     flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
                         cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON +
-                        cnt["searches"] * FLOP_SEARCH) / args.steps + lanes * FLOP_LANE
+                        cnt["searches"] * FLOP_SEARCH) / PROF_ITERS + lanes * FLOP_LANE
     br_s = branch_dispatch_ms * 1e-3
     achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
@@ -436,8 +449,10 @@ def main():
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": branch_traffic(),
                      "flops_per_launch": flops_per_launch, "launch_ms": branch_dispatch_ms,
                      "launch_ms_between_events": ktimes["branch"],
-                     "newton_iters_per_solve": cnt["newton"] / args.steps / lanes,
-                     "projected_searches_per_launch": cnt["searches"] / args.steps},
+                     "newton_iters_per_solve": cnt["newton"] / PROF_ITERS / lanes,
+                     "projected_searches_per_launch": cnt["searches"] / PROF_ITERS,
+                     "profiled_iterations": f"{PROF_ITERS} kernel-by-kernel iterations from the iterate after "
+                                            f"{max(PROF_FROM, args.warmup)}, after one untimed iteration"},
         "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps},
         "kernels_ms": ktimes,
         "profiled_ms_per_step": prof_ms_per_step,

@@ -146,6 +146,13 @@ int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes);
 /* Newton iterations of the last line solve, per (t, line): [T][n_line]. */
 int ucac_get_branch_iters(const ucac_handle* h, int32_t* iters);
 
+/* Start points of the last iteration that ran the learned start (ucac_set_warmstart),
+ * as the network predicted them, before any fallback: x0 [4][T][n_line] (host, FP32)
+ * holds v_i, v_j, theta_i, theta_j of every line solve (network outputs decoded:
+ * v = 1 + y0, 1 + y1; theta = angle target + y2 / 10, + y3 / 10).  Contents are
+ * unspecified if no iteration has run the learned start. */
+int ucac_get_line_starts(const ucac_handle* h, float* x0);
+
 /* Number of kernels in one inner iteration, in the order ucac_kernel_times
  * reports them: the unit side (per generator: the generator update, the UC
  * dynamic program and the relaxed commitments), lines (trust-region Newton; with

@@ -939,6 +939,20 @@ int ucac_get_branch_iters(const ucac_handle* hc, int32_t* iters) {
   return UCAC_OK;
 }
 
+int ucac_get_line_starts(const ucac_handle* hc, float* x0) {
+  ucac_handle* h = const_cast<ucac_handle*>(hc);
+  if (!h || !x0) return h ? fail(h, UCAC_E_INVAL, "null output") : UCAC_E_INVAL;
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  const size_t TL = (size_t)h->T * h->L;
+  std::vector<float> tmp(TL);
+  for (int k = 0; k < 4; ++k) {
+    if (TL) HIP_OR(h, hipMemcpy(tmp.data(), h->st.x0 + k * TL, sizeof(float) * TL, hipMemcpyDeviceToHost));
+    unpermute_rows(h->perm_line, (size_t)h->T, tmp.data(), x0 + k * TL);
+  }
+  return UCAC_OK;
+}
+
 int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots) {
   if (!h || !avg_ms || n_iters < 1 || n_slots < UCAC_N_KERNELS) return h ? fail(h, UCAC_E_INVAL, "bad arguments") : UCAC_E_INVAL;
   HIP_OR(h, hipSetDevice(h->par.device));
@@ -1168,6 +1182,7 @@ struct MlpCall {
   }
 };
 }  // namespace
+
 
 int ucac_mlp_create(int32_t device, uint64_t seed, ucac_mlp** out) {
   if (!out) return UCAC_E_INVAL;

@@ -89,6 +89,7 @@ def lib():
         L.ucac_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.ucac_set_state.argtypes = [vp, vp, C.c_size_t]
         L.ucac_get_branch_iters.argtypes = [vp, vp]
+        L.ucac_get_line_starts.argtypes = [vp, vp]
         L.ucac_last_error.argtypes = [vp]
         L.ucac_last_error.restype = C.c_char_p
         L.ucac_destroy.argtypes = [vp]
@@ -128,6 +129,7 @@ def lib():
         L.ucac_batch_destroy.restype = None
         for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
                      "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
+                     "ucac_get_line_starts",
                      "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones",
                      "ucac_set_warmstart", "ucac_log_pairs", "ucac_mlp_create", "ucac_mlp_set_weights",
                      "ucac_mlp_get_weights", "ucac_mlp_forward", "ucac_mlp_grad", "ucac_mlp_train",
@@ -264,6 +266,14 @@ def ucac_set_state(h, buf):
 def ucac_get_branch_iters(h, n_line, T):
     out = np.empty(T * n_line, dtype=np.int32)
     _check(lib().ucac_get_branch_iters(h, _ptr(out)), h)
+    return out
+
+
+def ucac_get_line_starts(h, n_line, T):
+    """The learned start's predicted points of the last learned-start iteration:
+    [4][T * n_line] (v_i, v_j, theta_i, theta_j), FP32."""
+    out = np.empty((4, T * n_line), dtype=np.float32)
+    _check(lib().ucac_get_line_starts(h, _ptr(out)), h)
     return out
 
 
@@ -437,6 +447,10 @@ class Solver:
 
     def set_warmstart(self, weights):
         ucac_set_warmstart(self.h, weights)
+
+    def line_starts(self):
+        N, L, G, T = self.dims
+        return ucac_get_line_starts(self.h, L, T)
 
     def set_params(self, **over):
         """Change parameters from the next iteration on (iterate and multipliers kept)."""

@@ -294,3 +294,33 @@ def test_trained_net_cuts_newton_work():
     o.step(200)
     compare(learned.get_state(), o.get_state(), inst, 1e-8, "trained learned start, 200 iterations")
     plain.close(), learned.close(), net.close()
+
+
+def test_line_start_points_match_oracle_network():
+    """The network inside the ADMM (the learned-start kernel that predicts each line
+    solve's Newton start): its decoded start points equal the FP64 oracle network
+    (BF16 rounding at the kernel's rounding points) applied to the host-computed
+    inputs of the same iteration, decoded the same way (v = 1 + y0, 1 + y1;
+    theta = angle target + y2 / 10, + y3 / 10), within the forward pass's tolerance."""
+    inst = synth.config_instance(1)
+    N, L, G, T = inst["n_bus"], inst["n_line"], inst["n_gen"], inst["T"]
+    g = ucac.Solver(inst)
+    g.step(30)
+    s0 = g.get_state()
+    rng = np.random.default_rng(31)
+    vec = om.init_params(17)
+    vec += rng.normal(0, 0.05, vec.size)  # nonzero biases, outputs away from zero
+    w = vec.astype(np.float32)
+    g.set_warmstart(w)
+    g.step(1)
+    x0 = g.line_starts().astype(np.float64)
+    ef, c = _expected_features(inst, g.params, s0)
+    y, _ = om.forward(w.astype(np.float64), ef.astype(np.float32).astype(np.float64), rounding=True)
+    ref = np.stack([1.0 + y[:, 0], 1.0 + y[:, 1], c[6].ravel() + 0.1 * y[:, 2], c[7].ravel() + 0.1 * y[:, 3]])
+    err_v = np.max(np.abs(x0[:2] - ref[:2]))
+    err_t = np.max(np.abs(x0[2:] - ref[2:]))
+    print(f"[mlp] start points vs oracle network: |dv| {err_v:.2e}, |dtheta| {err_t:.2e}", flush=True)
+    assert err_v <= 1e-2 and err_t <= 1e-3
+    raw = np.stack([x0[0] - 1.0, x0[1] - 1.0, 10.0 * (x0[2] - c[6].ravel()), 10.0 * (x0[3] - c[7].ravel())], axis=1)
+    assert _rel(raw, y) <= 2e-3
+    g.close()

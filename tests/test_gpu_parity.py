@@ -402,3 +402,58 @@ def test_set_params_midway_matches_oracle():
     with pytest.raises(ucac.UcacError):
         g.set_params(rho_pq=-1.0)
     g.step(1)  # the handle still works with its previous parameters
+
+
+def test_full_size_fifty_iterations():
+    """The 2000-bus, T = 24 workload from the cold start, 50 iterations in the
+    benchmark's launch configuration (graph replays), against 50 oracle iterations."""
+    inst = synth.config_instance(2)
+    g, o = pair(inst)
+    g.step(50)
+    o.step(50)
+    worst = compare(g.get_state(), o.get_state(), inst, 1e-8, "cfg2 it50")
+    print(f"[parity] cfg2 it50 worst {worst}", flush=True)
+
+
+@pytest.mark.parametrize("start", ["prev", "learned"])
+def test_full_size_warm_starts_one_iteration(start):
+    """The 2000-bus workload from a GPU iterate after 40 iterations: one iteration
+    with the previous-iterate Newton start (against the oracle doing the same, hold
+    step included), and one with the learned start (an untrained network: Newton from
+    its points reaches the flat start's solutions to the Newton tolerance, so the
+    oracle runs the plain method)."""
+    inst = synth.config_instance(2)
+    ws = 1 if start == "prev" else 0
+    g, o = pair(inst, warm_start=ws)
+    g.step(40)
+    o.set_state(g.get_state())
+    if start == "learned":
+        net = ucac.WarmStartNet(seed=8)
+        g.set_warmstart(net.get_weights())
+        net.close()
+    g.branch_counters(reset=True)
+    g.step(1)
+    o.step(1)
+    cnt = g.branch_counters()
+    print(f"[parity] cfg2 {start} start counters {cnt}", flush=True)
+    compare(g.get_state(), o.get_state(), inst, 1e-10 if start == "prev" else 1e-8, f"cfg2 {start}")
+
+
+def test_solve_mesh118_matches_oracle():
+    """The 118-bus workload solved to r_p, r_d <= 1e-4 from the cold start: the same
+    stopping iteration as the oracle, the same commitments, and the objective within
+    1e-6 relative."""
+    inst = synth.config_instance(1)
+    g, o = pair(inst)
+    rc_g, it_g = g.solve(1e-4, 6000)
+    rc_o, it_o = o.solve(1e-4, 6000)
+    print(f"[parity] mesh118 solve: gpu {rc_g} {it_g}, oracle {rc_o} {it_o}", flush=True)
+    assert rc_g == 0 and rc_o == 0
+    assert it_g == it_o
+    rp, rd, zinf, obj = g.residuals()
+    assert rp <= 1e-4 and rd <= 1e-4
+    assert obj == pytest.approx(o.objective(), rel=1e-6)
+    sol = g.solution()
+    S = o.state()
+    np.testing.assert_array_equal(sol["u_on"].ravel(), S["uon"].astype(np.int8))
+    compare(g.get_state(), o.get_state(), inst, 1e-6, "mesh118 solved")
