@@ -254,6 +254,23 @@ int ucac_mlp_forward(ucac_mlp* m, const float* x, int64_t n, float* y);
 /* Gradient of the mean squared error over the n samples and 4 outputs
  * (grad [UCAC_MLP_PARAMS], may be NULL) and the loss; weights unchanged. */
 int ucac_mlp_grad(ucac_mlp* m, const float* x, const float* t, int64_t n, float* grad, double* loss);
+/* ucac_mlp_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result as ucac_mlp_grad, with no allocation of any kind.
+ * x [n][20], t [n][4] (FP32), grad [UCAC_MLP_PARAMS] (FP32) and loss (one FP64) are
+ * DEVICE pointers owned by the caller; loss receives the sum of squared errors over
+ * the n samples and 4 outputs (ucac_mlp_grad's loss times 4n).  The call only
+ * enqueues the work on `stream` (a hipStream_t, NULL for the network's own stream)
+ * and returns: synchronize before reading the outputs.  The sample indices and the
+ * per-wavefront gradient partials live in one fixed device array per GPU (6.0 MB,
+ * held until the process ends), so n must lie in 1..UCAC_MLP_NOALLOC_MAX
+ * (UCAC_E_INVAL otherwise, with the limit in ucac_mlp_last_error).  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (on different streams,
+ * or from different threads) race and must be serialized by the caller.  The array
+ * keeps the last call's contents; each call writes every entry it reads first. */
+#define UCAC_MLP_NOALLOC_MAX 16384
+int ucac_mlp_grad_noalloc(ucac_mlp* m, const float* x, const float* t, int64_t n, float* grad, double* loss,
+                          void* stream);
 /* Adam (beta1 0.9, beta2 0.999, eps 1e-8) on shuffled mini-batches for `epochs`
  * passes over the n pairs; *last_loss = mean squared error of the last pass. */
 int ucac_mlp_train(ucac_mlp* m, const float* x, const float* t, int64_t n, int32_t epochs, int32_t batch, double lr,

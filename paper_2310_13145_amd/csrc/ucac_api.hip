@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1183,6 +1184,41 @@ struct MlpCall {
 };
 }  // namespace
 
+// ---- scratch of ucac_mlp_grad_noalloc ----------------------------------------------
+// One fixed array per GPU (each device holds its own copy until the process ends):
+// the sample indices of a call, then one gradient slot per wavefront of 64 samples.
+// Host code never uses the array's name as an address: the device address of each
+// GPU's copy is looked up once per device (hipGetSymbolAddress, with that device
+// current) when the first network is created on it, and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_IDX_BYTES = sizeof(int) * UCAC_MLP_NOALLOC_MAX;
+constexpr size_t NOALLOC_SLOT_OFF = (NOALLOC_IDX_BYTES + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_SLOT_OFF + sizeof(float) * (UCAC_MLP_NOALLOC_MAX / 64) * MLP_SLOT;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// Once per device, with that device current: the address of its copy of the array.
+void scratch_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+  g_scratch_done[device] = true;
+}
+
+__global__ void k_iota(int* idx, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) idx[i] = i;
+}
+}  // namespace
 
 int ucac_mlp_create(int32_t device, uint64_t seed, ucac_mlp** out) {
   if (!out) return UCAC_E_INVAL;
@@ -1205,6 +1241,7 @@ int ucac_mlp_create(int32_t device, uint64_t seed, ucac_mlp** out) {
   if ((e = hipMalloc(&m->m2, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "hipMalloc");
   if ((e = hipMemset(m->m1, 0, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "memset");
   if ((e = hipMemset(m->m2, 0, sizeof(float) * MLP_PARAMS)) != hipSuccess) return bad(e, "memset");
+  scratch_setup(device);  // this device current (set above)
   const MlpBufs b = mlp_carve(m->mem);
   if ((e = hipMemcpy(b.P, P.data(), sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice)) != hipSuccess) return bad(e, "upload");
   mlp_launch_pack(b.P, b.W1b, b.W2b, b.W3b, m->st);
@@ -1325,6 +1362,42 @@ int ucac_mlp_train(ucac_mlp* m, const float* x, const float* t, int64_t n, int32
   }
   MLP_OR(m, hipStreamSynchronize(m->st));
   if (last_loss) *last_loss = epoch_loss;
+  return UCAC_OK;
+}
+
+int ucac_mlp_grad_noalloc(ucac_mlp* m, const float* x, const float* t, int64_t n, float* grad, double* loss,
+                          void* stream) {
+  if (!m || !x || !t || !grad || !loss) return m ? (m->err = "null argument", UCAC_E_INVAL) : UCAC_E_INVAL;
+  if (n < 1 || n > UCAC_MLP_NOALLOC_MAX) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "n = %lld samples is outside 1..%d, the size of the fixed device scratch",
+             (long long)n, UCAC_MLP_NOALLOC_MAX);
+    m->err = buf;
+    return UCAC_E_INVAL;
+  }
+  if (m->device < 0 || m->device >= MAX_DEVICES) return m->err = "device ordinal out of range", UCAC_E_INVAL;
+  void* base = nullptr;
+  hipError_t serr = hipSuccess;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[m->device];
+    serr = g_scratch_err[m->device];
+  }
+  if (!base) return mfail(m, UCAC_E_DEVICE, "device scratch address (hipGetSymbolAddress)", serr);
+  MLP_OR(m, hipSetDevice(m->device));
+  hipStream_t st = stream ? (hipStream_t)stream : m->st;
+  int* idx = (int*)base;
+  float* slots = (float*)((unsigned char*)base + NOALLOC_SLOT_OFF);
+  const int nb = (int)n, waves = (nb + 63) / 64;
+  // identity sample order: every index the training kernel reads is written here first
+  hipLaunchKernelGGL(k_iota, dim3((nb + 255) / 256), dim3(256), 0, st, idx, nb);
+  MLP_OR(m, hipGetLastError());
+  const MlpBufs b = mlp_carve(m->mem);
+  // each wavefront overwrites its whole slot (every parameter and its loss sum), so the
+  // slots need no clearing; the reduction reads only this call's slots
+  mlp_launch_train(mlp_view(b), x, t, idx, nb, (float)(2.0 / (4.0 * (double)n)), slots, st);
+  mlp_launch_reduce(slots, waves, grad, loss, b.P, m->m1, m->m2, 0, 0.0f, b.W1b, b.W2b, b.W3b, st);
+  MLP_OR(m, hipGetLastError());
   return UCAC_OK;
 }
 

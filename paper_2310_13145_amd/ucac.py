@@ -108,6 +108,7 @@ def lib():
         L.ucac_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
         L.ucac_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, dp]
         L.ucac_mlp_train.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, dp]
+        L.ucac_mlp_grad_noalloc.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.ucac_mlp_last_error.argtypes = [vp]
         L.ucac_mlp_last_error.restype = C.c_char_p
         L.ucac_mlp_destroy.argtypes = [vp]
@@ -133,6 +134,7 @@ def lib():
                      "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones",
                      "ucac_set_warmstart", "ucac_log_pairs", "ucac_mlp_create", "ucac_mlp_set_weights",
                      "ucac_mlp_get_weights", "ucac_mlp_forward", "ucac_mlp_grad", "ucac_mlp_train",
+                     "ucac_mlp_grad_noalloc",
                      "ucac_batch_create", "ucac_batch_member", "ucac_batch_step", "ucac_batch_solve",
                      "ucac_batch_autotune", "ucac_batch_set_config", "ucac_batch_get_config"):
             getattr(L, name).restype = C.c_int
@@ -299,6 +301,7 @@ def ucac_branch_counters(h, reset=False):
 
 MLP_PARAMS = 5764
 MLP_IN, MLP_OUT = 20, 4
+MLP_NOALLOC_MAX = 16384
 
 
 def ucac_set_warmstart(h, weights):
@@ -367,6 +370,22 @@ class WarmStartNet:
         ls = C.c_double(0.0)
         _mcheck(lib().ucac_mlp_grad(self.m, _ptr(x), _ptr(t), x.shape[0], _ptr(g), C.byref(ls)), self.m)
         return g, ls.value
+
+    def grad_noalloc(self, x, t, grad, loss, stream=None):
+        """ucac_mlp_grad_noalloc on device tensors the caller owns: x [n, 20] and t [n, 4]
+        float32, grad [MLP_PARAMS] float32 and loss [1] float64 (written: the sum of
+        squared errors).  Enqueued on `stream` (a torch stream; default: the current one)."""
+        import torch
+        n = int(x.shape[0])
+        for a, shape, dt in ((x, (n, MLP_IN), torch.float32), (t, (n, MLP_OUT), torch.float32),
+                             (grad, (MLP_PARAMS,), torch.float32), (loss, (1,), torch.float64)):
+            if tuple(a.shape) != shape or a.dtype != dt or not a.is_cuda or not a.is_contiguous():
+                raise ValueError(f"expected a contiguous {dt} cuda tensor of shape {shape}, got {a.dtype} "
+                                 f"{tuple(a.shape)} on {a.device}")
+        st = (stream or torch.cuda.current_stream(x.device)).cuda_stream
+        _mcheck(lib().ucac_mlp_grad_noalloc(self.m, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), n,
+                                            C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                            C.c_void_p(st)), self.m)
 
     def train(self, x, t, epochs=10, batch=256, lr=1e-3, seed=0):
         x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, MLP_IN)
