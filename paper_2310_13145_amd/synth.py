@@ -15,7 +15,11 @@ stand-in with the parameter distributions below:
 * generators at distinct random buses: c2 ~ U(0.01, 0.1) $/MW^2h, c1 ~ U(10, 40) $/MWh,
   start-up cost ~ U(100, 500) $, Pmax ~ U(1, 3) p.u., Pmin = 0.2 Pmax,
   ramp and start-up/shut-down ramps 0.5 Pmax per period, min up/down ~ U{2, 3},
-  Qmax = 0.6 Pmax, Qmin = -0.3 Pmax, initially on at p0 = 0.5 Pmax;
+  reactive capability Qmax = 0.6 Pmax, Qmin = -0.6 Pmax (a unit absorbs as much as
+  it produces: the lines' charging b ~ U(0, 0.2) supplies about 0.1 p.u. per line,
+  far more than the light load's reactive demand, and with Qmin = -0.3 Pmax the
+  units cannot absorb the surplus within the voltage bounds in the light periods
+  of the 2000-bus mesh), initially on at p0 = 0.5 Pmax;
 * loads on round(2N/3) random buses, base ~ U(0.5, 1.5) rescaled so the base
   total is 30 % of the installed capacity (a light load, the same motive as the
   paper's demand discount; at 40 % and above the random placement of units and
@@ -130,7 +134,7 @@ def make_instance(n_bus, n_line, n_gen, T, seed, ring=False, load_frac=0.3):
         load_p=f64(load_p), load_q=f64(load_q),
         gen_bus=i32(gen_bus),
         gen_pmin=f64(0.2 * pmax), gen_pmax=f64(pmax),
-        gen_qmin=f64(-0.3 * pmax), gen_qmax=f64(0.6 * pmax),
+        gen_qmin=f64(-0.6 * pmax), gen_qmax=f64(0.6 * pmax),
         gen_c2=f64(c2), gen_c1=f64(c1), gen_cnl=f64(np.zeros(n_gen)),
         gen_csu=f64(csu), gen_csd=f64(np.zeros(n_gen)),
         gen_ru=f64(0.5 * pmax), gen_rd=f64(0.5 * pmax),
