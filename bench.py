@@ -192,10 +192,13 @@ def cpu_baseline(inst, seconds, state0=None):
 
 def time_to_tol(ucac, torch, inst, args):
     """Solve from the cold start to r_p, r_d <= tol with the flat and the previous-iterate
-    Newton start; the device records the first iteration under 1e-2, 1e-3 and 1e-4."""
+    Newton start, each with fixed penalties and with residual balancing of the penalty
+    classes (a decision after every 50th iteration); the device records the first
+    iteration under 1e-2, 1e-3 and 1e-4."""
     res = {}
-    for label, ws in (("plain", 0), ("prev_iterate", 1)):
-        s = ucac.Solver(inst, warm_start=ws)
+    for label, ws, adapt in (("plain", 0, 0), ("prev_iterate", 1, 0), ("plain_balanced", 0, 50),
+                             ("prev_iterate_balanced", 1, 50)):
+        s = ucac.Solver(inst, warm_start=ws, adapt_every=adapt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, iters = s.solve(args.tol, args.max_iters)
@@ -204,12 +207,19 @@ def time_to_tol(ucac, torch, inst, args):
         rp, rd, zinf, obj = s.residuals()
         ms = s.milestones()
         per_it = el / max(iters, 1)
+        if adapt:
+            S = ucac.split_state(s.get_state(), inst["n_bus"], inst["n_line"], inst["n_gen"], inst["T"])
+            pen = {k: S[k] for k in ("rho_pq", "rho_va", "rho_cpl", "rho_uc")}
+        else:
+            pen = None
         res[label] = {"converged": rc == 0, "iters": iters, "seconds": el, "r_p": rp, "r_d": rd, "objective": obj,
+                      "final_penalties": pen,
                       "first_iter_below": ms,
                       "seconds_to": {k: (v * per_it if v > 0 else None) for k, v in ms.items()}}
         s.close()
-    if res["plain"]["converged"] and res["prev_iterate"]["converged"]:
-        res["speedup_prev_iterate"] = res["plain"]["seconds"] / res["prev_iterate"]["seconds"]
+    for label in ("prev_iterate", "plain_balanced", "prev_iterate_balanced"):
+        if res["plain"]["converged"] and res[label]["converged"]:
+            res[f"speedup_{label}"] = res["plain"]["seconds"] / res[label]["seconds"]
     return res
 
 

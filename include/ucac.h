@@ -88,6 +88,23 @@ typedef struct {
   int32_t warm_start; /* [0] line Newton start: 0 flat (mid voltages, zero angles),
                          1 previous iterate, 2 learned (needs ucac_set_warmstart) */
   int32_t device;     /* [0] HIP device ordinal */
+  /* Residual balancing of the four penalty classes (power rows: line flows and
+   * generator consensus; voltage/angle rows; bound/ramp coupling rows; commitment
+   * rows), the remedy Sec. V names for the method's sensitivity to the penalties.
+   * After every adapt_every-th inner iteration (0: fixed penalties), per class:
+   * r = max |a_r + z_r| over its rows, s = rho max |change of the duplicates in its
+   * rows| / max |y_r| over its rows; rho times adapt_tau if r > adapt_mu s, divided
+   * by adapt_tau if s > adapt_mu r, within [rho / adapt_span, rho * adapt_span] of the
+   * configured value, at most adapt_max times per class, not for a class whose
+   * multipliers are all zero nor for one whose r and s are both at most 1e-9
+   * (rounding noise).  The penalties in force are part of the iterate
+   * (ucac_get_state); the multipliers are stored unscaled, so they stay valid.  With
+   * it on, every iteration runs its control step as a kernel of its own. */
+  int32_t adapt_every; /* [0] */
+  double adapt_mu;     /* [10] */
+  double adapt_tau;    /* [2] */
+  int32_t adapt_max;   /* [20] */
+  double adapt_span;   /* [100] */
 } ucac_params;
 
 /* Fill p with the defaults above. */
@@ -135,12 +152,13 @@ int ucac_get_solution(const ucac_handle* h, double* p, double* q, int8_t* u_on, 
 
 /* Full iterate as a flat FP64 array (line x-side, generator x-side, duplicates,
  * z/y/lambda of every row, then beta, ||z^{k-1}||, k, l, iteration count,
- * r_p, r_in, r_d, ||z||, converged flag).  With buf == NULL only *bytes is set.
+ * r_p, r_in, r_d, ||z||, converged flag, the penalties in force rho_pq, rho_va,
+ * rho_cpl, rho_uc and their residual-balancing change counts).  With buf == NULL only *bytes is set.
  * UCAC_E_STATE if *bytes is too small. */
 int ucac_get_state(const ucac_handle* h, void* buf, size_t* bytes);
 
 /* Replace the iterate (resume or inject).  UCAC_E_STATE if bytes differs from
- * the state size or the buffer holds NaN/Inf. */
+ * the state size, the buffer holds NaN/Inf, or a penalty in force is not positive. */
 int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes);
 
 /* Newton iterations of the last line solve, per (t, line): [T][n_line]. */
@@ -323,9 +341,10 @@ const char* ucac_batch_last_error(const ucac_batch* b);
 void ucac_batch_destroy(ucac_batch* b);
 
 /* Replace the parameters of a live handle (penalties, outer-loop and Newton
- * settings, tol, warm_start 0/1) from the next iteration on; the iterate,
- * multipliers and beta are kept (the multipliers are stored unscaled, so a
- * changed penalty leaves them valid).  A learned start loaded with
+ * settings, tol, warm_start 0/1, residual balancing) from the next iteration on;
+ * the iterate, multipliers and beta are kept (the multipliers are stored unscaled,
+ * so a changed penalty leaves them valid); the penalties in force become the new
+ * ones and their residual-balancing counts restart.  A learned start loaded with
  * ucac_set_warmstart stays in use.  device cannot change.  UCAC_E_INVAL for
  * invalid values (the handle is unchanged). */
 int ucac_set_params(ucac_handle* h, const ucac_params* params);

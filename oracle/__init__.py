@@ -25,7 +25,8 @@ _LIB = os.environ.get("UCAC_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 NRB = 8   # line rows: Pf Qf Pt Qt Wf Wt Thf Tht
 NRG = 11  # generator rows: G1 G2 C1..C6 U1 U2 U3
-SCALARS = ["beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r_d", "z_inf", "converged"]
+SCALARS = ["beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r_d", "z_inf", "converged",
+           "rho_pq", "rho_va", "rho_cpl", "rho_uc", "nchg_pq", "nchg_va", "nchg_cpl", "nchg_uc"]
 
 
 def build(verbose=False):
@@ -65,6 +66,8 @@ class Params(C.Structure):
         ("newton_max_iter", C.c_int32), ("newton_gtol", C.c_double),
         ("max_inner", C.c_int32), ("eps_in0", C.c_double), ("tol", C.c_double),
         ("warm_start", C.c_int32),
+        ("adapt_every", C.c_int32), ("adapt_mu", C.c_double), ("adapt_tau", C.c_double),
+        ("adapt_max", C.c_int32), ("adapt_span", C.c_double),
     ]
 
 

@@ -65,6 +65,12 @@ typedef struct {
   int32_t max_inner;
   double eps_in0, tol;
   int32_t warm_start; /* 0 flat start, 1 previous iterate */
+  /* residual balancing of the four penalty classes (0 = fixed penalties) */
+  int32_t adapt_every;   /* decide after every adapt_every-th inner iteration */
+  double adapt_mu;       /* imbalance factor */
+  double adapt_tau;      /* scaling factor of one change */
+  int32_t adapt_max;     /* at most this many changes per class */
+  double adapt_span;     /* a class's penalty stays within [rho0 / span, rho0 * span] */
 } orc_params;
 
 /* row indices */
@@ -85,7 +91,11 @@ typedef struct {
   double *sc; /* scalars: see SC_* */
 } orc_state;
 
-enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZINF, SC_CONV, NSC };
+enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZINF, SC_CONV,
+       SC_RHO_PQ, SC_RHO_VA, SC_RHO_CPL, SC_RHO_UC, SC_NCHG_PQ, SC_NCHG_VA, SC_NCHG_CPL, SC_NCHG_UC, NSC };
+/* penalty classes: power rows (line flows B1-B4, generator consensus G1-G2), voltage
+ * and angle rows (B5-B8), bound and ramp coupling rows (C1-C6), commitment rows (U1-U3) */
+enum { CL_PQ, CL_VA, CL_CPL, CL_UC, NCL };
 
 typedef struct {
   int N, L, G, T, ref;
@@ -685,6 +695,7 @@ void orc_params_default(orc_params *p) {
   p->newton_max_iter = 50; p->newton_gtol = 1e-12;
   p->max_inner = 1000; p->eps_in0 = 1e-2; p->tol = 1e-4;
   p->warm_start = 0;
+  p->adapt_every = 0; p->adapt_mu = 10.0; p->adapt_tau = 2.0; p->adapt_max = 20; p->adapt_span = 100.0;
 }
 
 static void init_state(orc_problem *P);
@@ -810,6 +821,8 @@ static void init_state(orc_problem *P) {
   }
   S->sc[SC_BETA] = P->par.beta0;
   S->sc[SC_ZPREV] = INFINITY;
+  S->sc[SC_RHO_PQ] = P->par.rho_pq; S->sc[SC_RHO_VA] = P->par.rho_va;
+  S->sc[SC_RHO_CPL] = P->par.rho_cpl; S->sc[SC_RHO_UC] = P->par.rho_uc;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -849,12 +862,19 @@ static void rows_gen(const orc_problem *P, int t, int g, double *a) {
   a[RG_U3] = S->usd[k] - S->ubsd[k];
 }
 
-static double rho_branch(const orc_problem *P, int r) { return r < 4 ? P->par.rho_pq : P->par.rho_va; }
+/* the penalties in force: part of the iterate (residual balancing may change them) */
+static double rho_pq(const orc_problem *P) { return P->st.sc[SC_RHO_PQ]; }
+static double rho_va(const orc_problem *P) { return P->st.sc[SC_RHO_VA]; }
+static double rho_cpl(const orc_problem *P) { return P->st.sc[SC_RHO_CPL]; }
+static double rho_uc(const orc_problem *P) { return P->st.sc[SC_RHO_UC]; }
+static double rho_branch(const orc_problem *P, int r) { return r < 4 ? rho_pq(P) : rho_va(P); }
 static double rho_gen(const orc_problem *P, int r) {
-  if (r <= RG_G2) return P->par.rho_pq;
-  if (r <= RG_C6) return P->par.rho_cpl;
-  return P->par.rho_uc;
+  if (r <= RG_G2) return rho_pq(P);
+  if (r <= RG_C6) return rho_cpl(P);
+  return rho_uc(P);
 }
+static int class_branch(int r) { return r < 4 ? CL_PQ : CL_VA; }
+static int class_gen(int r) { return r <= RG_G2 ? CL_PQ : (r <= RG_C6 ? CL_CPL : CL_UC); }
 
 /* ------------------------------------------------------------------------- */
 /* the six blocks of one inner iteration                                     */
@@ -890,7 +910,7 @@ static void block_uc(orc_problem *P, const xbar_view *X) {
       double y[3] = {S->yG[RG_U1][k], S->yG[RG_U2][k], S->yG[RG_U3][k]};
       for (int sp = 0; sp < 2; ++sp)
         for (int s = 0; s < 2; ++s)
-          Lt[((size_t)t * 2 + sp) * 2 + s] = uc_cost(P->cnl[g], P->csu[g], P->csd[g], P->par.rho_uc, sp, s, ub, z, y);
+          Lt[((size_t)t * 2 + sp) * 2 + s] = uc_cost(P->cnl[g], P->csu[g], P->csd[g], rho_uc(P), sp, s, ub, z, y);
     }
     dp_solve(T, Lt, P->u0[g], P->lon[g], P->loff[g], P->tu[g], P->td[g], u);
     for (int t = 0; t < T; ++t) {
@@ -911,7 +931,7 @@ static void gen_data_of(const orc_problem *P, int g, gen_data *d) {
   d->qlo_box = qbox_lo(P, g); d->qhi_box = qbox_hi(P, g);
   d->pmin = P->pmin[g]; d->pmaxc = P->pmax[g]; d->qmin = P->qmin[g]; d->qmax = P->qmax[g];
   d->ru = P->ru[g]; d->rd = P->rd[g]; d->su = P->su[g]; d->sd = P->sd[g];
-  d->rho_pq = P->par.rho_pq; d->rho_c = P->par.rho_cpl;
+  d->rho_pq = rho_pq(P); d->rho_c = rho_cpl(P);
 }
 
 /* step:opf, generator part */
@@ -939,7 +959,7 @@ static void block_gen(orc_problem *P, const xbar_view *X) {
 static void block_branch(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, L = P->L, N = P->N;
-  double gtol = P->par.newton_gtol * fmax(1.0, fmax(P->par.rho_pq, P->par.rho_va));
+  double gtol = P->par.newton_gtol * fmax(1.0, fmax(rho_pq(P), rho_va(P)));
 #pragma omp parallel for collapse(2) schedule(dynamic, 64)
   for (int t = 0; t < T; ++t) {
     for (int l = 0; l < L; ++l) {
@@ -957,7 +977,7 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
         double rho = rho_branch(P, r);
         b.c[r] = xb[r] - S->zB[r][k] - S->yB[r][k] / rho;
       }
-      b.rho_pq = P->par.rho_pq; b.rho_va = P->par.rho_va; b.mu = P->par.mu_line;
+      b.rho_pq = rho_pq(P); b.rho_va = rho_va(P); b.mu = P->par.mu_line;
       b.nu[0] = S->nuf[k]; b.nu[1] = S->nut[k];
       double x[4];
       if (P->par.warm_start == 1) {
@@ -984,7 +1004,7 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
 static void block_ubar(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
-  double ruc = P->par.rho_uc, rc = P->par.rho_cpl;
+  double ruc = rho_uc(P), rc = rho_cpl(P);
 #pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
     for (int g = 0; g < G; ++g) {
@@ -1029,7 +1049,7 @@ static void block_ubar(orc_problem *P, const xbar_view *X) {
 static void block_bus(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, L = P->L, N = P->N, G = P->G;
-  double rpq = P->par.rho_pq, rva = P->par.rho_va, rc = P->par.rho_cpl;
+  double rpq = rho_pq(P), rva = rho_va(P), rc = rho_cpl(P);
 #pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
     for (int i = 0; i < N; ++i) {
@@ -1109,15 +1129,17 @@ static void block_bus(orc_problem *P, const xbar_view *X) {
   }
 }
 
-/* step:z and step:y, then the residuals.  Returns nothing; fills the scalars. */
-static void block_duals(orc_problem *P) {
+/* step:z and step:y, then the residuals.  Fills the scalars and, per penalty class,
+ * the largest |a_r + z_r| (rin_c) and the largest |y_r| after the update (y_c). */
+static void block_duals(orc_problem *P, double *rin_c, double *y_c) {
   orc_state *S = &P->st;
   int T = P->T, L = P->L, G = P->G;
   double beta = S->sc[SC_BETA];
   double rp = 0.0, rin = 0.0, zinf = 0.0;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
   /* the line rows and the generator-side rows are two independent sets of items;
    * the residual maxima are exact whatever the order */
-#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf)
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf, r0, r1, y0, y1)
   for (int t = 0; t < T; ++t) {
     for (int l = 0; l < L; ++l) {
       size_t k = (size_t)t * L + l;
@@ -1129,10 +1151,12 @@ static void block_duals(orc_problem *P) {
         S->zB[r][k] = z;
         S->yB[r][k] += rho * (a[r] + z);
         rp = fmax(rp, fabs(a[r])); rin = fmax(rin, fabs(a[r] + z)); zinf = fmax(zinf, fabs(z));
+        if (class_branch(r) == CL_PQ) { r0 = fmax(r0, fabs(a[r] + z)); y0 = fmax(y0, fabs(S->yB[r][k])); }
+        else { r1 = fmax(r1, fabs(a[r] + z)); y1 = fmax(y1, fabs(S->yB[r][k])); }
       }
     }
   }
-#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf)
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rp, rin, zinf, r0, r2, r3, y0, y2, y3)
   for (int t = 0; t < T; ++t) {
     for (int g = 0; g < G; ++g) {
       size_t k = (size_t)t * G + g;
@@ -1144,10 +1168,51 @@ static void block_duals(orc_problem *P) {
         S->zG[r][k] = z;
         S->yG[r][k] += rho * (a[r] + z);
         rp = fmax(rp, fabs(a[r])); rin = fmax(rin, fabs(a[r] + z)); zinf = fmax(zinf, fabs(z));
+        int c = class_gen(r);
+        double ar = fabs(a[r] + z), yr = fabs(S->yG[r][k]);
+        if (c == CL_PQ) { r0 = fmax(r0, ar); y0 = fmax(y0, yr); }
+        else if (c == CL_CPL) { r2 = fmax(r2, ar); y2 = fmax(y2, yr); }
+        else { r3 = fmax(r3, ar); y3 = fmax(y3, yr); }
       }
     }
   }
   S->sc[SC_RP] = rp; S->sc[SC_RIN] = rin; S->sc[SC_ZINF] = zinf;
+  rin_c[CL_PQ] = r0; rin_c[CL_VA] = r1; rin_c[CL_CPL] = r2; rin_c[CL_UC] = r3;
+  y_c[CL_PQ] = y0; y_c[CL_VA] = y1; y_c[CL_CPL] = y2; y_c[CL_UC] = y3;
+}
+
+/* Residual balancing of the penalty classes, the remedy the paper's conclusion
+ * points to for its main limitation (convergence sensitive to rho_pq, rho_va, rho_uc).
+ * For class c: the primal residual r_c = max |a_r + z_r| over its rows, the dual
+ * residual s_c = rho_c max |xbar^{l+1} - xbar^l| over the duplicates its rows
+ * contain, divided by the class's multiplier scale max |y_r| (so both are relative
+ * and unit-free); rho_c doubles (times tau) when r_c > mu s_c and halves when
+ * s_c > mu r_c, within [rho0_c / span, rho0_c span] and at most adapt_max times per
+ * class.  A class whose multipliers are all zero carries no information and keeps
+ * its penalty, and so does a class whose two residuals are both at or below
+ * ADAPT_NOISE: rows satisfied to the rounding level (commitments equal to their
+ * binary duplicates, say), whose ratio is rounding noise.  The new penalties hold from the next iteration on; the multipliers
+ * are kept unscaled, so they stay valid. */
+#define ADAPT_NOISE 1e-9
+static void adapt_penalties(orc_problem *P, const double *rin_c, const double *dx_c, const double *y_c) {
+  orc_state *S = &P->st;
+  const int rho_slot[NCL] = {SC_RHO_PQ, SC_RHO_VA, SC_RHO_CPL, SC_RHO_UC};
+  const int cnt_slot[NCL] = {SC_NCHG_PQ, SC_NCHG_VA, SC_NCHG_CPL, SC_NCHG_UC};
+  const double rho0[NCL] = {P->par.rho_pq, P->par.rho_va, P->par.rho_cpl, P->par.rho_uc};
+  const double mu = P->par.adapt_mu, tau = P->par.adapt_tau, span = P->par.adapt_span;
+  for (int c = 0; c < NCL; ++c) {
+    if (S->sc[cnt_slot[c]] >= (double)P->par.adapt_max || !(y_c[c] > 0.0)) continue;
+    double rho = S->sc[rho_slot[c]];
+    double sd = rho * dx_c[c] / y_c[c];
+    if (!(rin_c[c] > ADAPT_NOISE || sd > ADAPT_NOISE)) continue; /* both at the rounding level */
+    if (rin_c[c] > mu * sd && rho * tau <= rho0[c] * span) {
+      S->sc[rho_slot[c]] = rho * tau;
+      S->sc[cnt_slot[c]] += 1.0;
+    } else if (sd > mu * rin_c[c] && rho / tau >= rho0[c] / span) {
+      S->sc[rho_slot[c]] = rho / tau;
+      S->sc[cnt_slot[c]] += 1.0;
+    }
+  }
 }
 
 /* step:outer */
@@ -1183,19 +1248,34 @@ static int iterate(orc_problem *P, int stop_at_tol) {
   block_branch(P, &X);   /* step:opf    lines */
   block_ubar(P, &X);     /* step:uc_bar (new x, old pbar) */
   block_bus(P, &X);      /* step:opf_bar (new x, old ubar) */
-  /* dual residual: largest change of any duplicate */
-  double rd = 0.0;
-  size_t nx = xbar_count(P);
-#pragma omp parallel for schedule(static) reduction(max : rd)
-  for (size_t k = 0; k < nx; ++k) rd = fmax(rd, fabs(S->wb[k] - P->xb_old[k]));
-  S->sc[SC_RD] = rd;
-  block_duals(P);        /* step:z, step:y */
+  /* dual residual: largest change of any duplicate; per penalty class, the largest
+   * change of the duplicates its rows contain (power: line-end flows, pbar, qbar;
+   * voltage/angle: wbar, thetabar; coupling: pbar and the relaxed commitments;
+   * commitment: the relaxed commitments) */
+  size_t TL = (size_t)P->T * P->L, TG = (size_t)P->T * P->G, TN = (size_t)P->T * P->N;
+  double d_va = 0.0, d_fl = 0.0, d_pb = 0.0, d_qb = 0.0, d_ub = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : d_va)
+  for (size_t k = 0; k < 2 * TN; ++k) d_va = fmax(d_va, fabs(S->wb[k] - P->xb_old[k]));
+#pragma omp parallel for schedule(static) reduction(max : d_fl)
+  for (size_t k = 2 * TN; k < 2 * TN + 4 * TL; ++k) d_fl = fmax(d_fl, fabs(S->wb[k] - P->xb_old[k]));
+#pragma omp parallel for schedule(static) reduction(max : d_pb)
+  for (size_t k = 2 * TN + 4 * TL; k < 2 * TN + 4 * TL + TG; ++k) d_pb = fmax(d_pb, fabs(S->wb[k] - P->xb_old[k]));
+#pragma omp parallel for schedule(static) reduction(max : d_qb)
+  for (size_t k = 2 * TN + 4 * TL + TG; k < 2 * TN + 4 * TL + 2 * TG; ++k) d_qb = fmax(d_qb, fabs(S->wb[k] - P->xb_old[k]));
+#pragma omp parallel for schedule(static) reduction(max : d_ub)
+  for (size_t k = 2 * TN + 4 * TL + 2 * TG; k < xbar_count(P); ++k) d_ub = fmax(d_ub, fabs(S->wb[k] - P->xb_old[k]));
+  S->sc[SC_RD] = fmax(fmax(d_va, d_fl), fmax(fmax(d_pb, d_qb), d_ub));
+  double dx_c[NCL] = {fmax(d_fl, fmax(d_pb, d_qb)), d_va, fmax(d_pb, d_ub), d_ub};
+  double rin_c[NCL], y_c[NCL];
+  block_duals(P, rin_c, y_c);  /* step:z, step:y */
   S->sc[SC_ITER] += 1.0;
   S->sc[SC_LIN] += 1.0;
   if (stop_at_tol && S->sc[SC_RP] <= P->par.tol && S->sc[SC_RD] <= P->par.tol) {
     S->sc[SC_CONV] = 1.0;
     return 1;
   }
+  if (P->par.adapt_every > 0 && fmod(S->sc[SC_ITER], (double)P->par.adapt_every) == 0.0)
+    adapt_penalties(P, rin_c, dx_c, y_c);
   if (fmax(S->sc[SC_RIN], S->sc[SC_RD]) <= eps_inner(P) || S->sc[SC_LIN] >= (double)P->par.max_inner)
     outer_update(P);
   return 0;
@@ -1221,7 +1301,15 @@ size_t orc_state_size(const orc_problem *P) { return P->n_state; }
 void orc_get_state(const orc_problem *P, double *out) { memcpy(out, P->buf, sizeof(double) * P->n_state); }
 void orc_set_state(orc_problem *P, const double *in) { memcpy(P->buf, in, sizeof(double) * P->n_state); }
 void orc_reset(orc_problem *P) { init_state(P); }
-void orc_set_params(orc_problem *P, const orc_params *par) { P->par = *par; }
+/* new parameters from the next iteration on; the penalties in force become the new
+ * ones and their residual-balancing counts restart */
+void orc_set_params(orc_problem *P, const orc_params *par) {
+  P->par = *par;
+  orc_state *S = &P->st;
+  S->sc[SC_RHO_PQ] = par->rho_pq; S->sc[SC_RHO_VA] = par->rho_va;
+  S->sc[SC_RHO_CPL] = par->rho_cpl; S->sc[SC_RHO_UC] = par->rho_uc;
+  S->sc[SC_NCHG_PQ] = S->sc[SC_NCHG_VA] = S->sc[SC_NCHG_CPL] = S->sc[SC_NCHG_UC] = 0.0;
+}
 void orc_get_branch_iters(const orc_problem *P, int32_t *out) {
   for (size_t k = 0; k < (size_t)P->T * P->L; ++k) out[k] = P->br_iters[k];
 }

@@ -63,6 +63,15 @@ __device__ inline void row_update(RowZY& r, double a, double rho, double beta, c
   zinf = nmax(zinf, fabs(z));
 }
 
+// row_update that also accumulates the row's class maxima |a + z| and |y| (residual
+// balancing); the row's own arithmetic is row_update's.
+__device__ inline void row_update_c(RowZY& r, double a, double rho, double beta, const LamUpd& lu, double& rp,
+                                    double& rin, double& zinf, double& rin_c, double& y_c) {
+  row_update(r, a, rho, beta, lu, rp, rin, zinf);
+  rin_c = nmax(rin_c, fabs(a + r.z));
+  y_c = nmax(y_c, fabs(r.y));
+}
+
 __device__ inline void row_store(const RowZY& r, double* zr, double* yr, double* lr, int k, const LamUpd& lu) {
   zr[k] = r.z;
   yr[k] = r.y;
@@ -172,12 +181,14 @@ __device__ inline UnitPre unit_pre(const UnitRaw& r, const Par& p, int t, int T)
 // unconditional (clamped indices; the contributions of unused slots are selected away
 // as +0.0, which leaves every sum exactly as if they were skipped), so that none of
 // them waits behind another; the sums keep the incidence order.
-__device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+__device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   const int N = n.N, G = n.G, T = n.T;
   const int TG = T * G;
   const int idx = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
+  double rin_pq = 0.0, y_pq = 0.0, dx_va = 0.0, dx_pq = 0.0, dx_pb = 0.0;  // class maxima
   if (idx < T * N) {
     const int t = idx / N, i = idx - t * N;
     const double rpq = p.rho_pq, rva = p.rho_va;
@@ -246,12 +257,15 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
     const double wnew = has_w ? tauw + (aw * mu1 + bw * mu2) / Ww : wold;
     const double thnew = (i == n.ref) ? 0.0 : (Wt > 0.0 ? St / Wt : thold);
     rd = nmax(fabs(wnew - wold), fabs(thnew - thold));
+    dx_va = rd;
     for (int e = g0; e < g1; ++e) {
       UnitPre v = e == g0 ? u0 : unit_pre(unit_raw(n, s, t, n.gen_list[e]), p, t, T);
       const double pn = v.Sp / v.Wp + mu1 / v.Wp, qn = v.tq + mu2 / rpq;
       rd = nmax(rd, nmax(fabs(pn - v.pold), fabs(qn - v.qold)));
-      row_update(v.r1, v.pv - pn, rpq, beta, lu, rp, rin, zinf);
-      row_update(v.r2, v.qv - qn, rpq, beta, lu, rp, rin, zinf);
+      dx_pb = nmax(dx_pb, fabs(pn - v.pold));
+      dx_pq = nmax(dx_pq, nmax(fabs(pn - v.pold), fabs(qn - v.qold)));
+      row_update_c(v.r1, v.pv - pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+      row_update_c(v.r2, v.qv - qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
       s.pb[v.k] = pn;
       s.qb[v.k] = qn;
       row_store(v.r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, v.k, lu);
@@ -265,13 +279,20 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bus + blk) * NACC);
+  if (p.adapt_every > 0) {
+    const double vc[5] = {rin_pq, y_pq, dx_va, dx_pq, dx_pb};
+    const int wc[5] = {CS_RIN + CL_PQ, CS_Y + CL_PQ, CS_DX + CL_VA, CS_DX + CL_PQ, CS_DX + CL_CPL};
+    block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bus + blk) * NCS);
+  }
 }
 
-__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   const int TL = n.T * n.L, TN = n.T * n.N;
   const int idx = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
+  double rin_pq = 0.0, rin_va = 0.0, y_pq = 0.0, y_va = 0.0;  // class maxima
   if (idx < TL) {
     const int t = idx / n.L, l = idx - t * n.L;
     const double rpq = p.rho_pq, rva = p.rho_va;
@@ -298,10 +319,10 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
       const EndData& q = d[side];
       const double Pn = q.tP - mu1[side] / rpq, Qn = q.tQ - mu2[side] / rpq;
       rd = nmax(rd, nmax(fabs(Pn - Pold[side]), fabs(Qn - Qold[side])));
-      row_update(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf);
-      row_update(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf);
-      row_update(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf);
-      row_update(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf);
+      row_update_c(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+      row_update_c(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+      row_update_c(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
+      row_update_c(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
       double* Pdup = side ? s.Pbt : s.Pbf;
       double* Qdup = side ? s.Qbt : s.Qbf;
       Pdup[q.k] = Pn;
@@ -314,6 +335,12 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
+  if (p.adapt_every > 0) {
+    // the line-end duplicates' change is this block's rd
+    const double vc[5] = {rin_pq, rin_va, y_pq, y_va, rd};
+    const int wc[5] = {CS_RIN + CL_PQ, CS_RIN + CL_VA, CS_Y + CL_PQ, CS_Y + CL_VA, CS_DX + CL_PQ};
+    block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bpost + blk) * NCS);
+  }
 }
 
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
@@ -325,11 +352,13 @@ __global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
   bus_body(M.n, M.s, M.p, blockIdx.x - b0, gr.blk_count[mk]);
 }
 
-__device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+__device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   const int G = n.G, TG = n.T * G;
   const int i = blk * BLOCK + threadIdx.x;
   double rp = 0.0, rin = 0.0, zinf = 0.0;
+  double rin_c = 0.0, rin_u = 0.0, y_c = 0.0, y_u = 0.0;  // class maxima (coupling, commitment rows)
   if (i < TG) {
     const int t = i / G, g = i - t * G;
     const double beta = s.sc[SC_BETA];
@@ -355,7 +384,10 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
 #pragma unroll
     for (int r = 0; r < 9; ++r) rz[r] = row_load(s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i);
 #pragma unroll
-    for (int r = 0; r < 9; ++r) row_update(rz[r], a[r], r < 6 ? p.rho_cpl : p.rho_uc, beta, lu, rp, rin, zinf);
+    for (int r = 0; r < 9; ++r) {
+      if (r < 6) row_update_c(rz[r], a[r], p.rho_cpl, beta, lu, rp, rin, zinf, rin_c, y_c);
+      else row_update_c(rz[r], a[r], p.rho_uc, beta, lu, rp, rin, zinf, rin_u, y_u);
+    }
 #pragma unroll
     for (int r = 0; r < 9; ++r) row_store(rz[r], s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i, lu);
     s.ubon[i] = uon;
@@ -365,6 +397,11 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
   const double v[3] = {rp, rin, zinf};
   const int which[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
   block_max_store<3>(v, which, s.red + (size_t)(s.red_gdual + blk) * NACC);
+  if (p.adapt_every > 0) {
+    const double vc[4] = {rin_c, rin_u, y_c, y_u};
+    const int wc[4] = {CS_RIN + CL_CPL, CS_RIN + CL_UC, CS_Y + CL_CPL, CS_Y + CL_UC};
+    block_max_store<4, NCS>(vc, wc, s.redc + (size_t)(s.red_gdual + blk) * NCS);
+  }
 }
 
 // step:opf_bar's line-end finish and the generator rows' multipliers in one launch:

@@ -543,8 +543,9 @@ __device__ __forceinline__ Line load_line(const Net& n, const State& s, const Pa
 enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
 
 template <int START, int BS>
-__device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p, const int blk) {
+__device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p0, const int blk) {
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   __shared__ double gh_lds[11][BS];
   const GHSave<BS> save{gh_lds};
   const int TL = n.T * n.L;
@@ -695,8 +696,9 @@ k_front_group(Group gu, Group gb, int grid_u, int slotT, int gpb) {
 // wavefront, and the launch spreads over every CU.
 constexpr int START_BLOCK = 64;
 
-__global__ void __launch_bounds__(START_BLOCK) k_line_start(Net n, State s, Par p) {
+__global__ void __launch_bounds__(START_BLOCK) k_line_start(Net n, State s, Par p0) {
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   extern __shared__ __bf16 lds_start[];
   const int TL = n.T * n.L;
   const int idx = blockIdx.x * START_BLOCK + threadIdx.x;

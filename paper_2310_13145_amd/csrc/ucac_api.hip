@@ -119,6 +119,13 @@ size_t state_doubles(size_t N, size_t L, size_t G, size_t T) {
   return T * L * (10 + 4 + 3 * NRB) + T * G * (11 + 5 + 3 * NRG) + T * N * 2 + NSC;
 }
 
+// residual balancing: adapt_every >= 0 (0 off), adapt_mu > 0, adapt_tau >= 1,
+// adapt_max >= 0, adapt_span >= 1, all finite
+bool adapt_params_ok(const ucac_params* p) {
+  return p->adapt_every >= 0 && p->adapt_max >= 0 && p->adapt_mu > 0.0 && std::isfinite(p->adapt_mu) &&
+         p->adapt_tau >= 1.0 && std::isfinite(p->adapt_tau) && p->adapt_span >= 1.0 && std::isfinite(p->adapt_span);
+}
+
 int validate(const ucac_network* n, const ucac_params* p) {
   if (!n || !p) return fail(nullptr, UCAC_E_INVAL, "null network or params");
   if (n->n_bus < 1 || n->n_line < 0 || n->n_gen < 0 || n->T < 1)
@@ -178,6 +185,7 @@ int validate(const ucac_network* n, const ucac_params* p) {
   if (!(p->theta > 0.0) || !(p->newton_gtol >= 0.0) || !(p->eps_in0 >= 0.0) || !(p->tol > 0.0) || p->newton_max_iter < 0 ||
       p->max_inner < 1 || p->warm_start < 0 || p->warm_start > 1)
     return fail(nullptr, UCAC_E_INVAL, "bad iteration parameters");
+  if (!adapt_params_ok(p)) return fail(nullptr, UCAC_E_INVAL, "bad residual-balancing parameters");
   return UCAC_OK;
 }
 
@@ -226,6 +234,7 @@ size_t carve(ucac_handle* h, char* base) {
   s.red_n = s.red_gdual + gen_dual_blocks(n);
   s.red_u = s.red_units;
   s.red = a.take<double>((size_t)(s.red_n + n.G) * NACC);
+  s.redc = a.take<double>((size_t)(s.red_n + n.G) * NCS);
   s.ebuf = a.take<double>(T * 2 * L * 4);
   s.bmu = a.take<double>(2 * T * N);
   s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
@@ -313,6 +322,7 @@ void cold_start(const ucac_network* n, const std::vector<double>& adm, const uca
     }
   sc[SC_BETA] = par.beta0;
   sc[SC_ZPREV] = INFINITY;
+  sc[SC_RHO_PQ] = par.rho_pq; sc[SC_RHO_VA] = par.rho_va; sc[SC_RHO_CPL] = par.rho_cpl; sc[SC_RHO_UC] = par.rho_uc;
 }
 
 // ---- locality ordering ------------------------------------------------------
@@ -447,6 +457,10 @@ Par kernel_params(const ucac_params& p) {
   Par k{};
   k.rho_pq = p.rho_pq; k.rho_va = p.rho_va; k.rho_uc = p.rho_uc; k.rho_cpl = p.rho_cpl; k.mu = p.mu_line;
   k.gtol = p.newton_gtol * std::fmax(1.0, std::fmax(p.rho_pq, p.rho_va));
+  k.gtol_base = p.newton_gtol;
+  k.adapt_every = p.adapt_every; k.adapt_max = p.adapt_max;
+  k.adapt_mu = p.adapt_mu; k.adapt_tau = p.adapt_tau; k.adapt_span = p.adapt_span;
+  k.rho0[CL_PQ] = p.rho_pq; k.rho0[CL_VA] = p.rho_va; k.rho0[CL_CPL] = p.rho_cpl; k.rho0[CL_UC] = p.rho_uc;
   k.tau = p.tau; k.theta = p.theta; k.lambda_max = p.lambda_max; k.beta_max = p.beta_max; k.eps_in0 = p.eps_in0;
   k.newton_max_iter = p.newton_max_iter; k.max_inner = p.max_inner; k.warm_start = p.warm_start;
   return k;
@@ -553,8 +567,11 @@ int build_graph(ucac_handle* h) {
 
 // Enqueue n iterations, largest graph first (solve mode: with a control-step kernel
 // after every iteration).
+// With residual balancing on, every iteration keeps its control-step kernel (the
+// solve-mode graphs, here without stopping): a control step may change the penalties,
+// which the next iteration's kernels read, so it cannot run beside them.
 hipError_t launch_iterations(ucac_handle* h, int n, bool solve = false) {
-  return (solve ? h->graphs_solve : h->graphs).launch(n, h->stream);
+  return (solve || h->kp.adapt_every > 0 ? h->graphs_solve : h->graphs).launch(n, h->stream);
 }
 
 // Write the host-owned control fields (never inside a captured graph).
@@ -602,6 +619,7 @@ void ucac_params_default(ucac_params* p) {
   p->newton_max_iter = 50; p->newton_gtol = 1e-12;
   p->max_inner = 1000; p->eps_in0 = 1e-2; p->tol = 1e-4;
   p->warm_start = 0; p->device = 0;
+  p->adapt_every = 0; p->adapt_mu = 10.0; p->adapt_tau = 2.0; p->adapt_max = 20; p->adapt_span = 100.0;
 }
 
 int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle** out) {
@@ -713,7 +731,8 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
       hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * NBRC * branch_waves(h)) != hipSuccess ||
-      hipMemset(h->st.red, 0, sizeof(double) * NACC * (h->st.red_n + h->net.G)) != hipSuccess)
+      hipMemset(h->st.red, 0, sizeof(double) * NACC * (h->st.red_n + h->net.G)) != hipSuccess ||
+      hipMemset(h->st.redc, 0, sizeof(double) * NCS * (h->st.red_n + h->net.G)) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
   if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);
@@ -920,6 +939,9 @@ int ucac_set_state(ucac_handle* h, const void* buf, size_t bytes) {
   for (size_t i = 0; i < h->n_state; ++i)
     if (!std::isfinite(d[i]) && !(i == h->n_state - NSC + SC_ZPREV && d[i] == INFINITY))
       return fail(h, UCAC_E_STATE, "state entry %zu is not finite", i);
+  // the penalties in force must be positive (every row divides by its penalty)
+  for (int k = SC_RHO_PQ; k <= SC_RHO_UC; ++k)
+    if (!(d[h->n_state - NSC + k] > 0.0)) return fail(h, UCAC_E_STATE, "state penalty scalar %d is not positive", k);
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
   std::vector<double> tmp(h->n_state);
@@ -1063,10 +1085,14 @@ int ucac_set_params(ucac_handle* h, const ucac_params* params) {
       !(params->mu_line > 0.0) || !(params->theta > 0.0) || !(params->newton_gtol >= 0.0) || !(params->eps_in0 >= 0.0) ||
       !(params->tol > 0.0) || params->newton_max_iter < 0 || params->max_inner < 1 || params->warm_start < 0 ||
       params->warm_start > 1 || !std::isfinite(params->rho_pq) || !std::isfinite(params->rho_va) ||
-      !std::isfinite(params->rho_uc) || !std::isfinite(params->rho_cpl) || !std::isfinite(params->mu_line))
+      !std::isfinite(params->rho_uc) || !std::isfinite(params->rho_cpl) || !std::isfinite(params->mu_line) ||
+      !adapt_params_ok(params))
     return fail(h, UCAC_E_INVAL, "invalid params");
   HIP_OR(h, hipSetDevice(h->par.device));
   HIP_OR(h, hipStreamSynchronize(h->stream));
+  // the penalties in force become the new ones; their residual-balancing counts restart
+  const double rho_now[8] = {params->rho_pq, params->rho_va, params->rho_cpl, params->rho_uc, 0.0, 0.0, 0.0, 0.0};
+  HIP_OR(h, hipMemcpy(h->st.sc + SC_RHO_PQ, rho_now, sizeof(rho_now), hipMemcpyHostToDevice));
   const bool learned = h->kp.warm_start == 2;
   const MlpView mlp = h->kp.mlp;
   h->par = *params;

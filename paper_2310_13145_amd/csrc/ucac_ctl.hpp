@@ -23,6 +23,38 @@ namespace ucac {
 
 constexpr int FIN_BLOCK = 256;  // largest block that runs the control step
 
+// Residual balancing of the penalty classes (the paper's conclusion names the
+// penalty choice as the method's main limitation).  Per class c, from this
+// iteration's class maxima: r_c = max |a + z| over its rows, s_c = rho_c max
+// |xbar change| over the duplicates in its rows / max |y| over its rows (both
+// relative); rho_c times tau when r_c > mu s_c, divided by tau when s_c > mu r_c,
+// within [rho0_c / span, rho0_c span], at most adapt_max times per class; not for a
+// class whose multipliers are all zero, nor for one whose two residuals are both at
+// or below ADAPT_NOISE (rows satisfied to the rounding level, e.g. commitments equal
+// to their binary duplicates: the ratio of two rounding errors decides nothing).  The
+// new penalties live in the iterate's scalars, which every kernel of the next
+// iteration reads.
+constexpr double ADAPT_NOISE = 1e-9;
+__device__ inline void adapt_penalties(double* sc, const Par& p, const double (&mc)[NCS]) {
+#pragma clang fp contract(off)
+  const int rho_slot[NCL] = {SC_RHO_PQ, SC_RHO_VA, SC_RHO_CPL, SC_RHO_UC};
+  const int cnt_slot[NCL] = {SC_NCHG_PQ, SC_NCHG_VA, SC_NCHG_CPL, SC_NCHG_UC};
+#pragma unroll
+  for (int c = 0; c < NCL; ++c) {
+    if (sc[cnt_slot[c]] >= (double)p.adapt_max || !(mc[CS_Y + c] > 0.0)) continue;
+    const double rho = sc[rho_slot[c]];
+    const double sd = rho * mc[CS_DX + c] / mc[CS_Y + c];
+    if (!(mc[CS_RIN + c] > ADAPT_NOISE || sd > ADAPT_NOISE)) continue;  // both at the rounding level
+    if (mc[CS_RIN + c] > p.adapt_mu * sd && rho * p.adapt_tau <= p.rho0[c] * p.adapt_span) {
+      sc[rho_slot[c]] = rho * p.adapt_tau;
+      sc[cnt_slot[c]] = sc[cnt_slot[c]] + 1.0;
+    } else if (sd > p.adapt_mu * mc[CS_RIN + c] && rho / p.adapt_tau >= p.rho0[c] / p.adapt_span) {
+      sc[rho_slot[c]] = rho / p.adapt_tau;
+      sc[cnt_slot[c]] = sc[cnt_slot[c]] + 1.0;
+    }
+  }
+}
+
 // The control step of one iteration, run by one whole block: reduce every per-block
 // residual slot of the iteration (the unit side's from slot units_slot on), advance the
 // counters and decide (see above).
@@ -67,12 +99,39 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
 #pragma unroll
     for (int k = 0; k < NACC; ++k) part[k][threadIdx.x >> 6] = m[k];
   }
+  // residual balancing after every adapt_every-th iteration: the per-class maxima of
+  // the same slots (a uniform condition: every thread read the same counter)
+  const bool adapt_now = p.adapt_every > 0 && fmod(it + 1.0, (double)p.adapt_every) == 0.0;
+  __shared__ double partc[NCS][FIN_BLOCK / 64];
+  double mc[NCS];
+#pragma unroll
+  for (int k = 0; k < NCS; ++k) mc[k] = 0.0;
+  if (adapt_now) {
+    for (int b = threadIdx.x; b < s.red_n; b += (int)blockDim.x) {
+      const int slot = b < s.red_bus ? units_slot + b : b;
+#pragma unroll
+      for (int k = 0; k < NCS; ++k) mc[k] = nmax(mc[k], s.redc[(size_t)slot * NCS + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NCS; ++k) mc[k] = wave_max(mc[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < NCS; ++k) partc[k][threadIdx.x >> 6] = mc[k];
+    }
+  }
   __syncthreads();
   if (threadIdx.x != 0 || halt) return;
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m[k] = nmax(m[k], part[k][w]);
     m[k] = nmax(m[k], part[k][0]);
+  }
+  if (adapt_now) {
+#pragma unroll
+    for (int k = 0; k < NCS; ++k) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mc[k] = nmax(mc[k], partc[k][w]);
+      mc[k] = nmax(mc[k], partc[k][0]);
+    }
   }
   const double rp = m[ACC_RP], rin = m[ACC_RIN], rd = m[ACC_RD], zinf = m[ACC_ZINF];
   sc[SC_RP] = rp;
@@ -92,6 +151,7 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
     c->halt = 1;
     return;
   }
+  if (adapt_now) adapt_penalties(sc, p, mc);
   const double eps = fmax(0.5 * tol, p.eps_in0 * ldexp(1.0, -(int)kout));
   if (fmax(rin, rd) <= eps || lin + 1.0 >= (double)p.max_inner) {
     c->pending = 1;

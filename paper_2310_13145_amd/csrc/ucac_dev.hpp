@@ -16,8 +16,18 @@ constexpr int NRB = 8;   // line rows: Pf Qf Pt Qt Wf Wt Thf Tht
 constexpr int NRG = 11;  // generator rows: G1 G2 C1..C6 U1 U2 U3
 enum { RB_PF, RB_QF, RB_PT, RB_QT, RB_WF, RB_WT, RB_TF, RB_TT };
 enum { RG_G1, RG_G2, RG_C1, RG_C2, RG_C3, RG_C4, RG_C5, RG_C6, RG_U1, RG_U2, RG_U3 };
-enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZINF, SC_CONV, NSC };
+// Iterate scalars.  The penalties in force are part of the iterate: residual
+// balancing (optional) changes them between iterations; every kernel reads them
+// here.
+enum { SC_BETA, SC_ZPREV, SC_KOUT, SC_LIN, SC_ITER, SC_RP, SC_RIN, SC_RD, SC_ZINF, SC_CONV,
+       SC_RHO_PQ, SC_RHO_VA, SC_RHO_CPL, SC_RHO_UC, SC_NCHG_PQ, SC_NCHG_VA, SC_NCHG_CPL, SC_NCHG_UC, NSC };
 enum { ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF, NACC };
+// Penalty classes: power rows (B1-B4, G1-G2), voltage and angle rows (B5-B8),
+// coupling rows (C1-C6), commitment rows (U1-U3); and the per-class maxima the
+// residual balancing needs (written only when it is on): |a + z| over the class's
+// rows, the change of the duplicates they contain, |y| after the update.
+enum { CL_PQ, CL_VA, CL_CPL, CL_UC, NCL };
+enum { CS_RIN = 0, CS_DX = NCL, CS_Y = 2 * NCL, NCS = 3 * NCL };
 
 constexpr int BLOCK = 256;
 // Line-kernel work counters per wavefront: evaluations, rejected trials, CG
@@ -86,6 +96,7 @@ struct State {
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks,
                                  // direct Newton steps, projected searches
   double* red;                   // [red_n][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
+  double* redc;                  // [red_n + G][NCS] the same slots' per-class maxima (residual balancing)
   int red_units, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
   // The unit side's slots have a second copy at red_n (G slots), so that an iteration's
   // control step can run beside the next iteration's unit blocks: red_u is where this
@@ -114,12 +125,30 @@ struct MlpView {
 };
 
 struct Par {
-  double rho_pq, rho_va, rho_uc, rho_cpl, mu;
-  double gtol;  // absolute projected-gradient tolerance
+  double rho_pq, rho_va, rho_uc, rho_cpl, mu;  // rho_*: the penalties in force (see live_par)
+  double gtol;       // absolute projected-gradient tolerance: gtol_base * max(1, rho_pq, rho_va)
+  double gtol_base;
   double tau, theta, lambda_max, beta_max, eps_in0;
   int newton_max_iter, max_inner, warm_start;  // warm_start 2: learned start from mlp
+  // residual balancing: every adapt_every-th iteration (0: off), factors mu and tau,
+  // at most adapt_max changes per class, within [rho0 / span, rho0 * span]
+  int adapt_every, adapt_max;
+  double adapt_mu, adapt_tau, adapt_span;
+  double rho0[NCL];  // the configured penalties (pq, va, cpl, uc)
   MlpView mlp;
 };
+
+// The parameters with the penalties in force, which live in the iterate's scalars
+// (uniform loads).  Every kernel body starts from these.
+__device__ inline Par live_par(const Par& p0, const State& s) {
+  Par p = p0;
+  p.rho_pq = s.sc[SC_RHO_PQ];
+  p.rho_va = s.sc[SC_RHO_VA];
+  p.rho_cpl = s.sc[SC_RHO_CPL];
+  p.rho_uc = s.sc[SC_RHO_UC];
+  p.gtol = p0.gtol_base * fmax(1.0, fmax(p.rho_pq, p.rho_va));
+  return p;
+}
 
 // ---- batched (grouped) launches ----------------------------------------------
 //
@@ -157,7 +186,7 @@ __device__ inline double wave_max(double v) {
 // 0).  The control step reduces the slots of every block.  One slot per block
 // instead of device-scope atomics on a few shared addresses: those serialize at
 // the memory side of the chip, across its XCDs' separate L2 caches.
-template <int NV>
+template <int NV, int W = NACC>
 __device__ inline void block_max_store(const double (&v)[NV], const int (&which)[NV], double* slot) {
   __shared__ double red[NV][BLOCK / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -170,7 +199,9 @@ __device__ inline void block_max_store(const double (&v)[NV], const int (&which)
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double out[NACC] = {0.0, 0.0, 0.0, 0.0};
+    double out[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) out[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double m = red[k][0];
@@ -178,7 +209,7 @@ __device__ inline void block_max_store(const double (&v)[NV], const int (&which)
       out[which[k]] = m;
     }
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) slot[k] = out[k];
+    for (int k = 0; k < W; ++k) slot[k] = out[k];
   }
 }
 

@@ -274,9 +274,10 @@ __device__ inline double ubar_item(const Net& n, const State& s, const Par& p, c
 // slotT: the horizon the LDS slots are sized for.  The largest star change of the
 // block goes to its residual slot.
 template <int BS>
-__device__ __forceinline__ void unit_body(const Net& n, const State& s, const Par& p, int blk, int slotT, int gpb) {
+__device__ __forceinline__ void unit_body(const Net& n, const State& s, const Par& p0, int blk, int slotT, int gpb) {
 #pragma clang fp contract(off)
   if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
   const int TPAR = BS / gpb;  // periods in flight per generator
   const int T = n.T, G = n.G;
   const int gsub = threadIdx.x % gpb, tb = threadIdx.x / gpb;
@@ -332,6 +333,12 @@ __device__ __forceinline__ void unit_body(const Net& n, const State& s, const Pa
   const double v[1] = {dmax};
   const int which[1] = {ACC_RD};
   block_max_store<1>(v, which, s.red + (size_t)(s.red_u + blk) * NACC);
+  if (p.adapt_every > 0) {
+    // the relaxed commitments are duplicates of both the coupling and the commitment rows
+    const double vc[2] = {dmax, dmax};
+    const int wc[2] = {CS_DX + CL_CPL, CS_DX + CL_UC};
+    block_max_store<2, NCS>(vc, wc, s.redc + (size_t)(s.red_u + blk) * NCS);
+  }
 }
 
 // Blocks for the unit side at gpb generators per block.

@@ -55,6 +55,8 @@ class ucac_params(C.Structure):
         ("newton_max_iter", C.c_int32), ("newton_gtol", C.c_double),
         ("max_inner", C.c_int32), ("eps_in0", C.c_double), ("tol", C.c_double),
         ("warm_start", C.c_int32), ("device", C.c_int32),
+        ("adapt_every", C.c_int32), ("adapt_mu", C.c_double), ("adapt_tau", C.c_double),
+        ("adapt_max", C.c_int32), ("adapt_span", C.c_double),
     ]
 
 
@@ -172,7 +174,8 @@ def make_network(inst):
 
 
 NRB, NRG = 8, 11
-SCALARS = ("beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r_d", "z_inf", "converged")
+SCALARS = ("beta", "znorm_prev", "k_outer", "l_inner", "iter", "r_p", "r_in", "r_d", "z_inf", "converged",
+           "rho_pq", "rho_va", "rho_cpl", "rho_uc", "nchg_pq", "nchg_va", "nchg_cpl", "nchg_uc")
 
 
 def state_layout(n_bus, n_line, n_gen, T):

@@ -36,7 +36,8 @@ def compare(sg, so, inst, rtol, label=""):
         if err > worst[0]:
             worst = (err, name)
         assert err <= rtol, f"{label}: {name} differs by {err:.3e} (tol {rtol:.1e})"
-    for k in ("beta", "k_outer", "l_inner", "iter", "converged"):
+    for k in ("beta", "k_outer", "l_inner", "iter", "converged", "rho_pq", "rho_va", "rho_cpl", "rho_uc",
+              "nchg_pq", "nchg_va", "nchg_cpl", "nchg_uc"):
         assert a[k] == b[k], f"{label}: scalar {k}: {a[k]} vs {b[k]}"
     for k in ("r_p", "r_in", "r_d", "z_inf", "znorm_prev"):
         if np.isfinite(b[k]):
@@ -457,3 +458,43 @@ def test_solve_mesh118_matches_oracle():
     S = o.state()
     np.testing.assert_array_equal(sol["u_on"].ravel(), S["uon"].astype(np.int8))
     compare(g.get_state(), o.get_state(), inst, 1e-6, "mesh118 solved")
+
+
+def _adapt_instance():
+    inst = synth.small_instance(14, 20, 5, 6, seed=83)
+    inst["gen_cnl"] = np.full(5, 40.0)
+    return inst
+
+
+def test_residual_balancing_matches_oracle():
+    """Residual balancing of the penalty classes with a small imbalance factor, so that
+    every class changes its penalty many times: 150 iterations (a decision after every
+    third) against the oracle doing the same; the penalties in force and their change
+    counts exactly, the iterate within 1e-8, after 50 and after 150 iterations."""
+    inst = _adapt_instance()
+    over = dict(adapt_every=3, adapt_mu=1.5, adapt_max=1000, adapt_span=1e6)
+    g, o = pair(inst, **over)
+    g.step(50)
+    o.step(50)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, "balancing it50")
+    g.step(100)
+    o.step(100)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, "balancing it150")
+    S = ucac.split_state(g.get_state(), *dims(inst))
+    print(f"[parity] balancing: changes pq {S['nchg_pq']:.0f} va {S['nchg_va']:.0f} cpl {S['nchg_cpl']:.0f} "
+          f"uc {S['nchg_uc']:.0f}", flush=True)
+    assert min(S["nchg_pq"], S["nchg_va"], S["nchg_cpl"], S["nchg_uc"]) > 0
+
+
+def test_residual_balancing_solve_mesh118():
+    """The 118-bus workload solved to 1e-4 with the default balancing settings
+    (a decision after every 50th iteration): the same stopping iteration, penalties and
+    commitments as the oracle, the objective within 1e-6."""
+    inst = synth.config_instance(1)
+    g, o = pair(inst, adapt_every=50)
+    rc_g, it_g = g.solve(1e-4, 6000)
+    rc_o, it_o = o.solve(1e-4, 6000)
+    print(f"[parity] mesh118 balanced solve: gpu {rc_g} {it_g}, oracle {rc_o} {it_o}", flush=True)
+    assert rc_g == 0 and rc_o == 0 and it_g == it_o
+    assert g.residuals()[3] == pytest.approx(o.objective(), rel=1e-6)
+    compare(g.get_state(), o.get_state(), inst, 1e-6, "mesh118 balanced solve")

@@ -23,6 +23,7 @@ CTRL = "tests/test_oracle_control.py"
 BLK = "tests/test_oracle_blocks.py"
 DPT = "tests/test_oracle_dp.py"
 SOL = "tests/test_oracle_solve.py"
+ADP = "tests/test_oracle_adapt.py"
 
 # (name, text in the oracle, replacement, occurrence, pins that must fail)
 MUTATIONS = [
@@ -37,8 +38,8 @@ MUTATIONS = [
     ("cost_units_kappa2", "net->gen_c2[g] * base * base", "net->gen_c2[g] * base", 0,
      [f"{CTRL}::test_objective_matches_cost_definition", f"{SOL}::test_single_bus_economic_dispatch"]),
     # residuals and the inner/outer control (Alg. alg:basic, step:outer)
-    ("rd_bus_duplicates_only", "for (size_t k = 0; k < nx; ++k) rd", "for (size_t k = 0; k < 2 * (size_t)P->T * P->N; ++k) rd",
-     0, [f"{CTRL}::test_residuals_recomputed_from_two_states"]),
+    ("rd_bus_duplicates_only", "S->sc[SC_RD] = fmax(fmax(d_va, d_fl), fmax(fmax(d_pb, d_qb), d_ub));",
+     "S->sc[SC_RD] = d_va;", 0, [f"{CTRL}::test_residuals_recomputed_from_two_states"]),
     ("rin_without_z_lines", "rin = fmax(rin, fabs(a[r] + z));", "rin = fmax(rin, fabs(a[r]));", 0,
      [f"{CTRL}::test_residuals_recomputed_from_two_states"]),
     ("rp_with_z_units", "rp = fmax(rp, fabs(a[r]));", "rp = fmax(rp, fabs(a[r] + z));", 1,
@@ -102,6 +103,25 @@ MUTATIONS = [
      [f"{BLK}::test_bus_block_with_shunts_and_ramp_rows"]),
     ("bus_reference_angle", "S->thb[bi] = (i == P->ref || Wt == 0.0)", "S->thb[bi] = (Wt == 0.0)", 0,
      [f"{SOL}::test_ac_power_flow_residual_at_convergence", f"{BLK}::test_bus_block_kkt"]),
+    # residual balancing of the penalty classes
+    ("adapt_direction_swapped", "S->sc[rho_slot[c]] = rho * tau;", "S->sc[rho_slot[c]] = rho / tau;", 0,
+     [f"{ADP}::test_decisions_follow_the_rule"]),
+    ("adapt_dual_not_normalised", "double sd = rho * dx_c[c] / y_c[c];", "double sd = rho * dx_c[c];", 0,
+     [f"{ADP}::test_decisions_follow_the_rule"]),
+    ("adapt_voltage_rows_as_power", "static int class_branch(int r) { return r < 4 ? CL_PQ : CL_VA; }",
+     "static int class_branch(int r) { return r < 6 ? CL_PQ : CL_VA; }", 0, [f"{ADP}::test_decisions_follow_the_rule"]),
+    ("adapt_coupling_change_without_pbar", "d_va, fmax(d_pb, d_ub), d_ub};", "d_va, d_ub, d_ub};", 0,
+     [f"{ADP}::test_decisions_follow_the_rule"]),
+    ("adapt_noise_floor_removed", "if (!(rin_c[c] > ADAPT_NOISE || sd > ADAPT_NOISE)) continue;", "", 0,
+     [f"{ADP}::test_rounding_level_class_keeps_its_penalty"]),
+    ("adapt_span_ignored", "rho * tau <= rho0[c] * span", "1", 0, [f"{ADP}::test_limits"]),
+    ("adapt_cap_off_by_one", "S->sc[cnt_slot[c]] >= (double)P->par.adapt_max", "S->sc[cnt_slot[c]] > (double)P->par.adapt_max",
+     0, [f"{ADP}::test_limits"]),
+    ("adapt_wrong_iteration", "fmod(S->sc[SC_ITER], (double)P->par.adapt_every)",
+     "fmod(S->sc[SC_ITER] + 1.0, (double)P->par.adapt_every)", 0, [f"{ADP}::test_decisions_follow_the_rule"]),
+    ("adapt_penalty_not_used", "static double rho_va(const orc_problem *P) { return P->st.sc[SC_RHO_VA]; }",
+     "static double rho_va(const orc_problem *P) { return P->par.rho_va; }", 0,
+     [f"{ADP}::test_equals_penalties_set_by_hand"]),
     # cold start
     ("cold_start_v_bound", "double x[4] = {0.5 * (P->vmin[i] + P->vmax[i]),", "double x[4] = {P->vmax[i],", 0,
      [f"{BLK}::test_initial_state_cold_start"]),
