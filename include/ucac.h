@@ -138,6 +138,22 @@ int ucac_step(ucac_handle* h, int32_t n_iters);
  * *iters_done (may be NULL) receives the iterations run by this call. */
 int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_done);
 
+/* UC warm start (Sec. IV-A: the commitments come from a multiperiod ACOPF solved
+ * first, each unit on or off by its generation level there).  Replaces the iterate:
+ * from the cold start, the same iteration with every commitment held at its
+ * cold-start value (all units on), no dynamic program, no commitment rows and no
+ * minimum-generation row -- the multiperiod ACOPF, generation anywhere in
+ * [0, P-bar] -- is solved to r_p, r_d <= tol or max_iters iterations (as
+ * ucac_solve); then a unit is committed in a period when its generation there is
+ * at least half its minimum output P-lo, and the iterate becomes the cold start
+ * with those commitments (start-ups and shut-downs from their changes, relaxed
+ * commitments equal to them, slacks feasible for them, multipliers zero, beta0).
+ * Returns the relaxed solve's status (UCAC_OK or UCAC_NOT_CONVERGED; the
+ * commitments are set either way) or a negative error; *iters_done (may be NULL)
+ * receives its iterations.  The parameters, the Newton start and a learned start
+ * stay as they were. */
+int ucac_uc_warmstart(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_done);
+
 /* Residuals of the current iterate: r_primal = max |A x + B xbar| over all
  * coupling rows (the paper's primal infeasibility), r_dual = max |xbar^{l+1} -
  * xbar^l|, z_inf = max |z|, objective = generation plus commitment cost.

@@ -68,6 +68,7 @@ class Params(C.Structure):
         ("warm_start", C.c_int32),
         ("adapt_every", C.c_int32), ("adapt_mu", C.c_double), ("adapt_tau", C.c_double),
         ("adapt_max", C.c_int32), ("adapt_span", C.c_double),
+        ("relax_uc", C.c_int32),
     ]
 
 
@@ -89,6 +90,8 @@ def lib():
         L.orc_step.argtypes = [vp, C.c_int]
         L.orc_solve.argtypes = [vp, C.c_double, C.c_int, ip]
         L.orc_solve.restype = C.c_int
+        L.orc_uc_warmstart.argtypes = [vp, C.c_double, C.c_int, ip]
+        L.orc_uc_warmstart.restype = C.c_int
         L.orc_state_size.argtypes = [vp]
         L.orc_state_size.restype = C.c_size_t
         L.orc_get_state.argtypes = [vp, vp]
@@ -210,6 +213,13 @@ class Oracle:
     def solve(self, tol=1e-4, max_iters=10000):
         it = C.c_int32(0)
         rc = lib().orc_solve(self.h, tol, int(max_iters), C.byref(it))
+        return rc, it.value
+
+    def uc_warmstart(self, tol=1e-3, max_iters=2000):
+        """UC warm start: relaxed multiperiod ACOPF, commitments rounded from its
+        generation levels, then the cold start with those commitments."""
+        it = C.c_int32(0)
+        rc = lib().orc_uc_warmstart(self.h, float(tol), int(max_iters), C.byref(it))
         return rc, it.value
 
     def state_size(self):

@@ -71,6 +71,9 @@ typedef struct {
   double adapt_tau;      /* scaling factor of one change */
   int32_t adapt_max;     /* at most this many changes per class */
   double adapt_span;     /* a class's penalty stays within [rho0 / span, rho0 * span] */
+  /* 1: the multiperiod ACOPF of the UC warm start (commitments fixed at their cold
+   * start, no DP, no commitment rows, no minimum-generation row) */
+  int32_t relax_uc;
 } orc_params;
 
 /* row indices */
@@ -475,6 +478,7 @@ typedef struct {
   double k2, k1, pmax, qlo_box, qhi_box;
   double pmin, pmaxc, qmin, qmax, ru, rd, su, sd;
   double rho_pq, rho_c;
+  int relax; /* the multiperiod ACOPF: no minimum-generation row C1 */
 } gen_data;
 
 /* in: pbar_t, qbar_t, pbar_{t-1}, ubar_on_t, ubar_on_{t-1}, ubar_su_t, ubar_sd_t,
@@ -488,7 +492,7 @@ static void gen_solve(const gen_data *d, double pb, double qb, double pb_prev, d
   double e2 = -d->pmaxc * uon + z[RG_C2] + y[RG_C2] / rc;
   double e5 = -pb_prev + d->rd * uon + d->sd * usd + z[RG_C5] + y[RG_C5] / rc;
   double e6 = -pb_prev - d->ru * uon_prev - d->su * usu + z[RG_C6] + y[RG_C6] / rc;
-  pwl fp = {2.0 * d->k2 + rp, d->k1 + rp * eG1, 4, {rc, rc, rc, rc}, {e1, e2, e5, e6}, {1, 0, 1, 0}};
+  pwl fp = {2.0 * d->k2 + rp, d->k1 + rp * eG1, 4, {d->relax ? 0.0 : rc, rc, rc, rc}, {e1, e2, e5, e6}, {1, 0, 1, 0}};
   double p = pwl_argmin(&fp, 0.0, d->pmax);
   /* q part: rows G2, C3 (-s3), C4 (+s4) */
   double eG2 = -qb + z[RG_G2] + y[RG_G2] / rp;
@@ -696,9 +700,11 @@ void orc_params_default(orc_params *p) {
   p->max_inner = 1000; p->eps_in0 = 1e-2; p->tol = 1e-4;
   p->warm_start = 0;
   p->adapt_every = 0; p->adapt_mu = 10.0; p->adapt_tau = 2.0; p->adapt_max = 20; p->adapt_span = 100.0;
+  p->relax_uc = 0;
 }
 
-static void init_state(orc_problem *P);
+static void init_state_u(orc_problem *P, const int8_t *u);
+static void init_state(orc_problem *P) { init_state_u(P, NULL); }
 
 orc_problem *orc_create(const orc_net *net, const orc_params *par) {
   orc_problem *P = (orc_problem *)calloc(1, sizeof(orc_problem));
@@ -773,9 +779,10 @@ static double qbox_lo(const orc_problem *P, int g) { return fmin(0.0, P->qmin[g]
 static double qbox_hi(const orc_problem *P, int g) { return fmax(0.0, P->qmax[g]); }
 
 /* Cold start: p, q and v at the middle of their bounds, angles zero, flows from
- * the voltages, duplicates equal to their originals, every unit committed,
- * slacks at their feasible values, multipliers zero, beta = beta0. */
-static void init_state(orc_problem *P) {
+ * the voltages, duplicates equal to their originals, the commitments u ([T][G],
+ * or every unit committed when u is NULL) with start-ups and shut-downs from their
+ * changes, slacks at their feasible values, multipliers zero, beta = beta0. */
+static void init_state_u(orc_problem *P, const int8_t *u) {
   orc_state *S = &P->st;
   int N = P->N, L = P->L, G = P->G, T = P->T;
   memset(P->buf, 0, sizeof(double) * P->n_state);
@@ -800,8 +807,9 @@ static void init_state(orc_problem *P) {
       S->p[k] = 0.5 * P->pmax[g];
       S->q[k] = 0.5 * (qbox_lo(P, g) + qbox_hi(P, g));
       S->pb[k] = S->p[k]; S->qb[k] = S->q[k];
-      int prev = t == 0 ? P->u0[g] : 1;
-      S->uon[k] = 1.0; S->usu[k] = (1 - prev) > 0 ? 1.0 : 0.0; S->usd[k] = 0.0;
+      int on = u ? u[k] : 1;
+      int prev = t == 0 ? P->u0[g] : (u ? u[k - G] : 1);
+      S->uon[k] = (double)on; S->usu[k] = (on - prev) > 0 ? 1.0 : 0.0; S->usd[k] = (prev - on) > 0 ? 1.0 : 0.0;
       S->ubon[k] = S->uon[k]; S->ubsu[k] = S->usu[k]; S->ubsd[k] = S->usd[k];
     }
   }
@@ -897,6 +905,7 @@ static xbar_view old_view(const orc_problem *P) {
 static void block_uc(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
+  if (P->par.relax_uc) return; /* the multiperiod ACOPF has no commitment decisions */
 #pragma omp parallel
   {
   double *Lt = (double *)malloc(sizeof(double) * 4 * (T > 0 ? T : 1));
@@ -932,6 +941,7 @@ static void gen_data_of(const orc_problem *P, int g, gen_data *d) {
   d->pmin = P->pmin[g]; d->pmaxc = P->pmax[g]; d->qmin = P->qmin[g]; d->qmax = P->qmax[g];
   d->ru = P->ru[g]; d->rd = P->rd[g]; d->su = P->su[g]; d->sd = P->sd[g];
   d->rho_pq = rho_pq(P); d->rho_c = rho_cpl(P);
+  d->relax = P->par.relax_uc;
 }
 
 /* step:opf, generator part */
@@ -1004,6 +1014,7 @@ static void block_branch(orc_problem *P, const xbar_view *X) {
 static void block_ubar(orc_problem *P, const xbar_view *X) {
   orc_state *S = &P->st;
   int T = P->T, G = P->G;
+  if (P->par.relax_uc) return; /* commitments fixed at their cold-start values */
   double ruc = rho_uc(P), rc = rho_cpl(P);
 #pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < T; ++t) {
@@ -1163,6 +1174,8 @@ static void block_duals(orc_problem *P, double *rin_c, double *y_c) {
       double a[NRG];
       rows_gen(P, t, g, a);
       for (int r = 0; r < NRG; ++r) {
+        /* the multiperiod ACOPF has no minimum-generation and no commitment rows */
+        if (P->par.relax_uc && (r == RG_C1 || r >= RG_U1)) continue;
         double rho = rho_gen(P, r);
         double z = -(S->lG[r][k] + S->yG[r][k] + rho * a[r]) / (beta + rho);
         S->zG[r][k] = z;
@@ -1295,6 +1308,31 @@ int orc_solve(orc_problem *P, double tol, int max_iters, int *iters_done) {
   for (i = 0; i < max_iters && !done; ++i) done = iterate(P, 1);
   if (iters_done) *iters_done = i;
   return done ? 0 : 1;
+}
+
+/* UC warm start (Sec. IV-A): solve the multiperiod ACOPF -- the same iteration with
+ * the commitments held at their cold-start values, no dynamic program, no commitment
+ * rows and no minimum-generation row, so that a unit's output may fall to zero --
+ * from the cold start to tol (or max_iters iterations); then commit a unit in a
+ * period when its generation there is at least half its minimum output, and start
+ * the method from the cold start with those commitments.  Returns the relaxed
+ * solve's status (0 converged, 1 not). */
+int orc_uc_warmstart(orc_problem *P, double tol, int max_iters, int *iters_done) {
+  orc_params saved = P->par;
+  P->par.relax_uc = 1;
+  init_state(P);
+  int rc = orc_solve(P, tol, max_iters, iters_done);
+  size_t TG = (size_t)P->T * P->G;
+  int8_t *u = (int8_t *)malloc(TG > 0 ? TG : 1);
+  for (int t = 0; t < P->T; ++t)
+    for (int g = 0; g < P->G; ++g) {
+      size_t k = (size_t)t * P->G + g;
+      u[k] = P->st.p[k] >= 0.5 * P->pmin[g] ? 1 : 0;
+    }
+  P->par = saved;
+  init_state_u(P, u);
+  free(u);
+  return rc;
 }
 
 size_t orc_state_size(const orc_problem *P) { return P->n_state; }

@@ -385,6 +385,9 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
     for (int r = 0; r < 9; ++r) rz[r] = row_load(s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i);
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
+      // the multiperiod ACOPF has no minimum-generation row (C1) and no commitment
+      // rows (U1-U3): their z, y stay as they are and they count in no residual
+      if (p.relax_uc && (r == 0 || r >= 6)) continue;
       if (r < 6) row_update_c(rz[r], a[r], p.rho_cpl, beta, lu, rp, rin, zinf, rin_c, y_c);
       else row_update_c(rz[r], a[r], p.rho_uc, beta, lu, rp, rin, zinf, rin_u, y_u);
     }

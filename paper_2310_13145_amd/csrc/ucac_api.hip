@@ -57,6 +57,8 @@ struct GraphSet {
 struct HostGen {
   std::vector<double> k2, k1, cnl, csu, csd;
   std::vector<int> u0;
+  // for the UC warm start's restart (internal order)
+  std::vector<double> pmin, pmax, qmin, qmax, ru, rd, su, sd, p0;
 };
 
 }  // namespace
@@ -79,6 +81,7 @@ struct ucac_handle {
   GraphSet graphs_solve;  // solve mode: GRAPH_SIZES[j] iterations, each with its own control-step kernel
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
+  std::vector<double> cold;  // the cold-start iterate (internal layout)
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
   // ucac_solve's snapshot at the start of each chunk: state, control block, work counters
@@ -325,6 +328,41 @@ void cold_start(const ucac_network* n, const std::vector<double>& adm, const uca
   sc[SC_RHO_PQ] = par.rho_pq; sc[SC_RHO_VA] = par.rho_va; sc[SC_RHO_CPL] = par.rho_cpl; sc[SC_RHO_UC] = par.rho_uc;
 }
 
+// A cold-start iterate S (internal layout) with the commitments u [T][G] (0/1)
+// instead of every unit committed: start-ups and shut-downs from their changes (u0
+// before the first period), relaxed commitments equal to them, and the slacks at
+// their feasible values for them (the same expressions as the cold start).
+void set_commitments(const HostGen& hg, size_t N, size_t L, size_t G, size_t T, std::vector<double>& S,
+                     const std::vector<signed char>& u) {
+  const size_t TL = T * L, TG = T * G, TN = T * N;
+  double* c = S.data() + 10 * TL;  // after the line x-side
+  double *p = c, *q = c + TG, *s = c + 2 * TG, *uon = c + 8 * TG, *usu = c + 9 * TG, *usd = c + 10 * TG;
+  c += 11 * TG + 2 * TN + 4 * TL;  // the generator x-side, bus duplicates, line-end duplicates
+  double *pb = c, *ubon = c + 2 * TG, *ubsu = c + 3 * TG, *ubsd = c + 4 * TG;
+  for (size_t t = 0; t < T; ++t)
+    for (size_t g = 0; g < G; ++g) {
+      const size_t k = t * G + g;
+      const int on = u[k], prev = t == 0 ? hg.u0[g] : u[k - G];
+      uon[k] = (double)on;
+      usu[k] = on > prev ? 1.0 : 0.0;
+      usd[k] = prev > on ? 1.0 : 0.0;
+      ubon[k] = uon[k]; ubsu[k] = usu[k]; ubsd[k] = usd[k];
+    }
+  for (size_t t = 0; t < T; ++t)
+    for (size_t g = 0; g < G; ++g) {
+      const size_t k = t * G + g;
+      const double pbp = t == 0 ? hg.p0[g] : pb[k - G];
+      const double uonp = t == 0 ? (double)hg.u0[g] : ubon[k - G];
+      const double pv = p[k], qv = q[k], uu = ubon[k];
+      s[0 * TG + k] = std::fmax(0.0, pv - hg.pmin[g] * uu);
+      s[1 * TG + k] = std::fmax(0.0, hg.pmax[g] * uu - pv);
+      s[2 * TG + k] = std::fmax(0.0, qv - hg.qmin[g] * uu);
+      s[3 * TG + k] = std::fmax(0.0, hg.qmax[g] * uu - qv);
+      s[4 * TG + k] = std::fmax(0.0, pv - pbp + hg.rd[g] * uu + hg.sd[g] * ubsd[k]);
+      s[5 * TG + k] = std::fmax(0.0, -(pv - pbp) + hg.ru[g] * uonp + hg.su[g] * ubsu[k]);
+    }
+}
+
 // ---- locality ordering ------------------------------------------------------
 //
 // The bus kernel gathers the x-side values of every incident line end and the line
@@ -461,6 +499,7 @@ Par kernel_params(const ucac_params& p) {
   k.adapt_every = p.adapt_every; k.adapt_max = p.adapt_max;
   k.adapt_mu = p.adapt_mu; k.adapt_tau = p.adapt_tau; k.adapt_span = p.adapt_span;
   k.rho0[CL_PQ] = p.rho_pq; k.rho0[CL_VA] = p.rho_va; k.rho0[CL_CPL] = p.rho_cpl; k.rho0[CL_UC] = p.rho_uc;
+  k.relax_uc = 0;
   k.tau = p.tau; k.theta = p.theta; k.lambda_max = p.lambda_max; k.beta_max = p.beta_max; k.eps_in0 = p.eps_in0;
   k.newton_max_iter = p.newton_max_iter; k.max_inner = p.max_inner; k.warm_start = p.warm_start;
   return k;
@@ -679,8 +718,14 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   h->hg.csu.assign(net->gen_csu, net->gen_csu + G);
   h->hg.csd.assign(net->gen_csd, net->gen_csd + G);
   h->hg.u0.assign(net->gen_u0, net->gen_u0 + G);
+  h->hg.pmin.assign(net->gen_pmin, net->gen_pmin + G); h->hg.pmax.assign(net->gen_pmax, net->gen_pmax + G);
+  h->hg.qmin.assign(net->gen_qmin, net->gen_qmin + G); h->hg.qmax.assign(net->gen_qmax, net->gen_qmax + G);
+  h->hg.ru.assign(net->gen_ru, net->gen_ru + G); h->hg.rd.assign(net->gen_rd, net->gen_rd + G);
+  h->hg.su.assign(net->gen_su, net->gen_su + G); h->hg.sd.assign(net->gen_sd, net->gen_sd + G);
+  h->hg.p0.assign(net->gen_p0, net->gen_p0 + G);
   std::vector<double> S;
   cold_start(net, adm, *params, S);
+  h->cold = S;
 
   h->arena_bytes = carve(h, nullptr);
   if (hipMalloc(&h->arena, h->arena_bytes) != hipSuccess) {
@@ -849,6 +894,40 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
   rc = check_bad(h);
   if (rc) return rc;
   return h->h_sc[SC_CONV] != 0.0 ? UCAC_OK : UCAC_NOT_CONVERGED;
+}
+
+int ucac_uc_warmstart(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_done) {
+  if (!h) return UCAC_E_INVAL;
+  if (!(tol > 0.0) || max_iters < 0) return fail(h, UCAC_E_INVAL, "bad tol or max_iters");
+  HIP_OR(h, hipSetDevice(h->par.device));
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  const Par kp_saved = h->kp;
+  const ucac_params par_saved = h->par;
+  // the multiperiod ACOPF, from the cold start
+  h->kp.relax_uc = 1;
+  int rc = build_graph(h);
+  if (rc) { h->kp = kp_saved; return rc; }
+  HIP_OR(h, hipMemcpy(h->d_state, h->cold.data(), sizeof(double) * h->n_state, hipMemcpyHostToDevice));
+  int32_t it = 0;
+  const int src = ucac_solve(h, tol, max_iters, &it);
+  h->kp = kp_saved;
+  h->par = par_saved;
+  rc = build_graph(h);
+  if (src < 0) return src;
+  if (rc) return rc;
+  // commitments from the generation levels: on where p >= P_lo / 2
+  const size_t TG = (size_t)h->T * h->G, TL = (size_t)h->T * h->L;
+  std::vector<double> p(TG);
+  if (TG) HIP_OR(h, hipMemcpy(p.data(), h->d_state + 10 * TL, sizeof(double) * TG, hipMemcpyDeviceToHost));
+  std::vector<signed char> u(TG);
+  for (size_t k = 0; k < TG; ++k) u[k] = p[k] >= 0.5 * h->hg.pmin[k % h->G] ? 1 : 0;
+  std::vector<double> S = h->cold;
+  set_commitments(h->hg, h->N, h->L, h->G, h->T, S, u);
+  HIP_OR(h, hipMemcpy(h->d_state, S.data(), sizeof(double) * h->n_state, hipMemcpyHostToDevice));
+  rc = set_ctl(h, 0, h->par.tol);
+  if (rc) return rc;
+  if (iters_done) *iters_done = it;
+  return src;
 }
 
 int ucac_residuals(const ucac_handle* hc, double* r_primal, double* r_dual, double* z_inf, double* objective) {

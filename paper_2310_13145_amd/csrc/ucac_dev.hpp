@@ -134,6 +134,9 @@ struct Par {
   // at most adapt_max changes per class, within [rho0 / span, rho0 * span]
   int adapt_every, adapt_max;
   double adapt_mu, adapt_tau, adapt_span;
+  // 1: the multiperiod ACOPF of the UC warm start (commitments held at their cold
+  // start, no dynamic program, no commitment rows U1-U3, no minimum-generation row C1)
+  int relax_uc;
   double rho0[NCL];  // the configured penalties (pq, va, cpl, uc)
   MlpView mlp;
 };

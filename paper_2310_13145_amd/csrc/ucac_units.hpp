@@ -149,7 +149,8 @@ __device__ inline void gen_item(const Net& n, const State& s, const Par& p, cons
   Pwl<4> fp;
   fp.A = 2.0 * n.k2[g] + rp;
   fp.B = n.k1[g] + rp * eG1;
-  fp.w[0] = rc; fp.w[1] = rc; fp.w[2] = rc; fp.w[3] = rc;
+  fp.w[0] = p.relax_uc ? 0.0 : rc;  // the multiperiod ACOPF has no minimum-generation row
+  fp.w[1] = rc; fp.w[2] = rc; fp.w[3] = rc;
   fp.e[0] = e1; fp.e[1] = e2; fp.e[2] = e5; fp.e[3] = e6;
   fp.neg[0] = true; fp.neg[1] = false; fp.neg[2] = true; fp.neg[3] = false;
   const double pv = fp.argmin(0.0, n.pmax[g]);
@@ -286,6 +287,27 @@ __device__ __forceinline__ void unit_body(const Net& n, const State& s, const Pa
 
   if (act)
     for (int t = tb; t < T; t += TPAR) gen_item(n, s, p, t * G + g);
+  if (p.relax_uc) {
+    // the multiperiod ACOPF: no commitment decisions; the relaxed commitments keep
+    // their values (copied to where the generator-row kernel commits them from)
+    const int TG = T * G;
+    if (act)
+      for (int t = tb; t < T; t += TPAR) {
+        const int k = t * G + g;
+        s.ub_nxt[k] = s.ubon[k];
+        s.ub_nxt[TG + k] = s.ubsu[k];
+        s.ub_nxt[2 * TG + k] = s.ubsd[k];
+      }
+    const double v[1] = {0.0};
+    const int which[1] = {ACC_RD};
+    block_max_store<1>(v, which, s.red + (size_t)(s.red_u + blk) * NACC);
+    if (p.adapt_every > 0) {
+      const double vc[2] = {0.0, 0.0};
+      const int wc[2] = {CS_DX + CL_CPL, CS_DX + CL_UC};
+      block_max_store<2, NCS>(vc, wc, s.redc + (size_t)(s.red_u + blk) * NCS);
+    }
+    return;
+  }
 
   extern __shared__ double lds_units[];
   char* base = (char*)lds_units + dp_slot_bytes(slotT) * gsub;

@@ -87,6 +87,7 @@ def lib():
         L.ucac_step.argtypes = [vp, C.c_int32]
         L.ucac_solve.argtypes = [vp, C.c_double, C.c_int32, ip]
         L.ucac_residuals.argtypes = [vp, dp, dp, dp, dp]
+        L.ucac_uc_warmstart.argtypes = [vp, C.c_double, C.c_int32, ip]
         L.ucac_get_solution.argtypes = [vp] * 8
         L.ucac_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.ucac_set_state.argtypes = [vp, vp, C.c_size_t]
@@ -130,7 +131,7 @@ def lib():
         L.ucac_batch_last_error.restype = C.c_char_p
         L.ucac_batch_destroy.argtypes = [vp]
         L.ucac_batch_destroy.restype = None
-        for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals",
+        for name in ("ucac_create", "ucac_set_stream", "ucac_step", "ucac_solve", "ucac_residuals", "ucac_uc_warmstart",
                      "ucac_get_solution", "ucac_get_state", "ucac_set_state", "ucac_get_branch_iters",
                      "ucac_get_line_starts",
                      "ucac_kernel_times", "ucac_branch_counters", "ucac_solve_milestones",
@@ -440,6 +441,14 @@ class Solver:
 
     def solve(self, tol=1e-4, max_iters=20000):
         return ucac_solve(self.h, tol, max_iters)
+
+    def uc_warmstart(self, tol=1e-3, max_iters=2000):
+        """UC warm start: the multiperiod ACOPF solved first, commitments from its
+        generation levels, then the cold start with them; (status, iterations)."""
+        it = C.c_int32(0)
+        rc = lib().ucac_uc_warmstart(self.h, float(tol), int(max_iters), C.byref(it))
+        _check(rc, self.h, ok=(UCAC_OK, UCAC_NOT_CONVERGED))
+        return rc, it.value
 
     def residuals(self):
         return ucac_residuals(self.h)

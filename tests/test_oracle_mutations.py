@@ -24,6 +24,7 @@ BLK = "tests/test_oracle_blocks.py"
 DPT = "tests/test_oracle_dp.py"
 SOL = "tests/test_oracle_solve.py"
 ADP = "tests/test_oracle_adapt.py"
+UCW = "tests/test_oracle_ucwarm.py"
 
 # (name, text in the oracle, replacement, occurrence, pins that must fail)
 MUTATIONS = [
@@ -122,6 +123,17 @@ MUTATIONS = [
     ("adapt_penalty_not_used", "static double rho_va(const orc_problem *P) { return P->st.sc[SC_RHO_VA]; }",
      "static double rho_va(const orc_problem *P) { return P->par.rho_va; }", 0,
      [f"{ADP}::test_equals_penalties_set_by_hand"]),
+    # UC warm start (the multiperiod ACOPF, then the commitments from its generation levels)
+    ("ucwarm_threshold_full_pmin", "u[k] = P->st.p[k] >= 0.5 * P->pmin[g] ? 1 : 0;", "u[k] = P->st.p[k] >= P->pmin[g] ? 1 : 0;", 0,
+     [f"{UCW}::test_rounding_and_restart"]),
+    ("relax_keeps_min_generation_row", "{d->relax ? 0.0 : rc, rc, rc, rc}", "{rc, rc, rc, rc}", 0,
+     [f"{UCW}::test_relaxed_run_is_the_multiperiod_acopf"]),
+    ("relax_runs_the_dp", "if (P->par.relax_uc) return; /* the multiperiod ACOPF has no commitment decisions */", "", 0,
+     [f"{UCW}::test_relaxed_run_is_the_multiperiod_acopf"]),
+    ("relax_updates_every_row", "if (P->par.relax_uc && (r == RG_C1 || r >= RG_U1)) continue;", "", 0,
+     [f"{UCW}::test_relaxed_run_is_the_multiperiod_acopf"]),
+    ("ucwarm_restart_keeps_relaxed_state", "  P->par = saved;\n  init_state_u(P, u);", "  P->par = saved;", 0,
+     [f"{UCW}::test_rounding_and_restart"]),
     # cold start
     ("cold_start_v_bound", "double x[4] = {0.5 * (P->vmin[i] + P->vmax[i]),", "double x[4] = {P->vmax[i],", 0,
      [f"{BLK}::test_initial_state_cold_start"]),
