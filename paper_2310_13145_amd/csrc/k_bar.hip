@@ -19,85 +19,10 @@
 //            U1..U3, which also commits the new relaxed commitments.
 // Each kernel stores its blocks' residual maxima into per-block slots.
 #include "ucac_launch.hpp"
+#include "ucac_rows.hpp"
+#include "ucac_ctl.hpp"
 
 namespace ucac {
-
-// A step:outer multiplier update decided by the previous iteration's control is
-// applied here, by the kernel that owns the row, just before the row's z update
-// (the multiplier is read nowhere else): lambda <- clamp(lambda + beta_prev z_prev).
-struct LamUpd {
-  bool on;
-  double b, lm;
-};
-
-__device__ inline LamUpd lambda_pending(const State& s, const Par& p) {
-  LamUpd u;
-  u.on = s.ctl->pending != 0;
-  u.b = s.ctl->beta_for_lambda;
-  u.lm = p.lambda_max;
-  return u;
-}
-
-// step:z and step:y of one row with value a = (Ax + Bxbar)_r, in three parts so that
-// a lane issues the loads of all its rows before its first store (a store may
-// alias any later load, so interleaving them costs one memory round trip per row):
-//   z <- -(lambda + y + rho a) / (beta + rho),  y <- y + rho (a + z),
-// with a pending step:outer update lambda <- clamp(lambda + beta_prev z_prev) first.
-// The residual maxima r_p = |a|, r_in = |a + z| and ||z|| are accumulated.
-struct RowZY {
-  double z, y, l;
-};
-
-__device__ inline RowZY row_load(const double* zr, const double* yr, const double* lr, int k) {
-  return RowZY{zr[k], yr[k], lr[k]};
-}
-
-__device__ inline void row_update(RowZY& r, double a, double rho, double beta, const LamUpd& lu, double& rp, double& rin,
-                                  double& zinf) {
-  if (lu.on) r.l = clampd(r.l + lu.b * r.z, -lu.lm, lu.lm);
-  const double z = -(r.l + r.y + rho * a) / (beta + rho);
-  r.y = r.y + rho * (a + z);
-  r.z = z;
-  rp = nmax(rp, fabs(a));
-  rin = nmax(rin, fabs(a + z));
-  zinf = nmax(zinf, fabs(z));
-}
-
-// row_update that also accumulates the row's class maxima |a + z| and |y| (residual
-// balancing); the row's own arithmetic is row_update's.
-__device__ inline void row_update_c(RowZY& r, double a, double rho, double beta, const LamUpd& lu, double& rp,
-                                    double& rin, double& zinf, double& rin_c, double& y_c) {
-  row_update(r, a, rho, beta, lu, rp, rin, zinf);
-  rin_c = nmax(rin_c, fabs(a + r.z));
-  y_c = nmax(y_c, fabs(r.y));
-}
-
-__device__ inline void row_store(const RowZY& r, double* zr, double* yr, double* lr, int k, const LamUpd& lu) {
-  zr[k] = r.z;
-  yr[k] = r.y;
-  if (lu.on) lr[k] = r.l;
-}
-
-
-
-struct EndData {
-  int k, rP, rQ, rW, rT;
-  double fP, fQ, v, th, tP, tQ;
-};
-
-__device__ inline EndData load_end(const Net& n, const State& s, int t, int TL, int code, double rpq) {
-  EndData d;
-  const int l = code >> 1, side = code & 1;
-  d.k = t * n.L + l;
-  d.rP = side ? RB_PT : RB_PF; d.rQ = side ? RB_QT : RB_QF; d.rW = side ? RB_WT : RB_WF; d.rT = side ? RB_TT : RB_TF;
-  d.fP = side ? s.pt[d.k] : s.pf[d.k];
-  d.fQ = side ? s.qt[d.k] : s.qf[d.k];
-  d.v = side ? s.vt[d.k] : s.vf[d.k];
-  d.th = side ? s.tht[d.k] : s.thf[d.k];
-  d.tP = d.fP + s.zB[d.rP * TL + d.k] + s.yB[d.rP * TL + d.k] / rpq;
-  d.tQ = d.fQ + s.zB[d.rQ * TL + d.k] + s.yB[d.rQ * TL + d.k] / rpq;
-  return d;
-}
 
 // The consensus and next-period ramp terms of unit g at bus-side item k = t * G + g
 // (the previous relaxed commitments): weight Wp and weighted centre Sp of pbar_t,
@@ -181,7 +106,10 @@ __device__ inline UnitPre unit_pre(const UnitRaw& r, const Par& p, int t, int T)
 // unconditional (clamped indices; the contributions of unused slots are selected away
 // as +0.0, which leaves every sum exactly as if they were skipped), so that none of
 // them waits behind another; the sums keep the incidence order.
-__device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
+// ROWS = false: the bus solve alone (the fused iteration: rows G1, G2 are updated by
+// the next launch's unit blocks, from the duplicates stored here).
+template <bool ROWS>
+__device__ __forceinline__ void bus_body_t(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
   if (s.ctl->halt) return;
   const Par p = live_par(p0, s);
   const int N = n.N, G = n.G, T = n.T;
@@ -264,12 +192,16 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
       rd = nmax(rd, nmax(fabs(pn - v.pold), fabs(qn - v.qold)));
       dx_pb = nmax(dx_pb, fabs(pn - v.pold));
       dx_pq = nmax(dx_pq, nmax(fabs(pn - v.pold), fabs(qn - v.qold)));
-      row_update_c(v.r1, v.pv - pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
-      row_update_c(v.r2, v.qv - qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+      if (ROWS) {
+        row_update_c(v.r1, v.pv - pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+        row_update_c(v.r2, v.qv - qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+      }
       s.pb[v.k] = pn;
       s.qb[v.k] = qn;
-      row_store(v.r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, v.k, lu);
-      row_store(v.r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, v.k, lu);
+      if (ROWS) {
+        row_store(v.r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, v.k, lu);
+        row_store(v.r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, v.k, lu);
+      }
     }
     s.wb[idx] = wnew;
     s.thb[idx] = thnew;
@@ -279,71 +211,34 @@ __device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bus + blk) * NACC);
-  if (p.adapt_every > 0) {
+  if (ROWS && p.adapt_every > 0) {
     const double vc[5] = {rin_pq, y_pq, dx_va, dx_pq, dx_pb};
     const int wc[5] = {CS_RIN + CL_PQ, CS_Y + CL_PQ, CS_DX + CL_VA, CS_DX + CL_PQ, CS_DX + CL_CPL};
     block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bus + blk) * NCS);
   }
 }
 
-__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
-  if (s.ctl->halt) return;
-  const Par p = live_par(p0, s);
-  const int TL = n.T * n.L, TN = n.T * n.N;
-  const int idx = blk * BLOCK + threadIdx.x;
-  double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
-  double rin_pq = 0.0, rin_va = 0.0, y_pq = 0.0, y_va = 0.0;  // class maxima
-  if (idx < TL) {
-    const int t = idx / n.L, l = idx - t * n.L;
-    const double rpq = p.rho_pq, rva = p.rho_va;
-    const double beta = s.sc[SC_BETA];
-    const LamUpd lu = lambda_pending(s, p);
-    // every load of both ends first, then the updates, then the stores
-    EndData d[2];
-    double mu1[2], mu2[2], wnew[2], thnew[2], Pold[2], Qold[2];
-    RowZY r[2][4];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      d[side] = load_end(n, s, t, TL, 2 * l + side, rpq);
-      const int b = t * n.N + (side ? n.to[l] : n.from[l]);
-      mu1[side] = s.bmu[b]; mu2[side] = s.bmu[TN + b]; wnew[side] = s.wb[b]; thnew[side] = s.thb[b];
-      const int k = d[side].k;
-      Pold[side] = side ? s.Pbt[k] : s.Pbf[k];
-      Qold[side] = side ? s.Qbt[k] : s.Qbf[k];
-      const int rows[4] = {d[side].rP, d[side].rQ, d[side].rW, d[side].rT};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) r[side][q] = row_load(s.zB + rows[q] * TL, s.yB + rows[q] * TL, s.lB + rows[q] * TL, k);
-    }
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const EndData& q = d[side];
-      const double Pn = q.tP - mu1[side] / rpq, Qn = q.tQ - mu2[side] / rpq;
-      rd = nmax(rd, nmax(fabs(Pn - Pold[side]), fabs(Qn - Qold[side])));
-      row_update_c(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
-      row_update_c(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
-      row_update_c(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
-      row_update_c(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
-      double* Pdup = side ? s.Pbt : s.Pbf;
-      double* Qdup = side ? s.Qbt : s.Qbf;
-      Pdup[q.k] = Pn;
-      Qdup[q.k] = Qn;
-      const int rows[4] = {q.rP, q.rQ, q.rW, q.rT};
-#pragma unroll
-      for (int w = 0; w < 4; ++w) row_store(r[side][w], s.zB + rows[w] * TL, s.yB + rows[w] * TL, s.lB + rows[w] * TL, q.k, lu);
-    }
-  }
-  const double v[4] = {rp, rin, rd, zinf};
-  const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
-  block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
-  if (p.adapt_every > 0) {
-    // the line-end duplicates' change is this block's rd
-    const double vc[5] = {rin_pq, rin_va, y_pq, y_va, rd};
-    const int wc[5] = {CS_RIN + CL_PQ, CS_RIN + CL_VA, CS_Y + CL_PQ, CS_Y + CL_VA, CS_DX + CL_PQ};
-    block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bpost + blk) * NCS);
-  }
+__device__ __forceinline__ void bus_body(const Net& n, const State& s, const Par& p, const int blk, const int nblk) {
+  bus_body_t<true>(n, s, p, blk, nblk);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_bus(Net n, State s, Par p) { bus_body(n, s, p, blockIdx.x, gridDim.x); }
+
+// The second launch of the fused iteration: the bus solve without rows G1, G2 (its
+// blocks write their residual slots from s.red_bus on, the copy the caller chose), and
+// with has_fin set, a first block that runs the previous iteration's control step over
+// the slot ranges fin.  That step writes nothing the bus solve reads: the penalties
+// stay fixed (no residual balancing), the stop flag is never set (step mode), and the
+// multiplier step and beta it may decide are read only by the next launch's row updates.
+__global__ void __launch_bounds__(BLOCK) k_bus_fused(Net n, State s, Par p, SlotRanges fin, int has_fin) {
+  static_assert(BLOCK == FIN_BLOCK, "the control step runs as one block of this launch");
+  int b = blockIdx.x;
+  if (has_fin) {
+    if (b == 0) { finalize_ranges(s, p, fin); return; }
+    --b;
+  }
+  bus_body_t<false>(n, s, p, b, (int)gridDim.x - has_fin);
+}
 
 __global__ void __launch_bounds__(BLOCK) k_bus_group(Group gr) {
   const int mk = gr.blk_member[blockIdx.x];
@@ -363,39 +258,7 @@ __device__ __forceinline__ void gen_dual_body(const Net& n, const State& s, cons
     const int t = i / G, g = i - t * G;
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
-    const double* nx_on = s.ub_nxt;
-    const double* nx_su = s.ub_nxt + TG;
-    const double* nx_sd = s.ub_nxt + 2 * TG;
-    const double uon = nx_on[i], usu = nx_su[i], usd = nx_sd[i];
-    const double uonp = t == 0 ? (double)n.u0[g] : nx_on[i - G];
-    const double pbp = t == 0 ? n.p0[g] : s.pb[i - G];
-    const double pv = s.p[i], qv = s.q[i];
-    double a[9];
-    a[0] = pv - s.s[0 * TG + i] - n.pmin[g] * uon;
-    a[1] = pv + s.s[1 * TG + i] - n.pmax[g] * uon;
-    a[2] = qv - s.s[2 * TG + i] - n.qmin[g] * uon;
-    a[3] = qv + s.s[3 * TG + i] - n.qmax[g] * uon;
-    a[4] = pv - pbp - s.s[4 * TG + i] + n.rd[g] * uon + n.sd[g] * usd;
-    a[5] = pv - pbp + s.s[5 * TG + i] - n.ru[g] * uonp - n.su[g] * usu;
-    a[6] = s.uon[i] - uon;
-    a[7] = s.usu[i] - usu;
-    a[8] = s.usd[i] - usd;
-    RowZY rz[9];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) rz[r] = row_load(s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i);
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      // the multiperiod ACOPF has no minimum-generation row (C1) and no commitment
-      // rows (U1-U3): their z, y stay as they are and they count in no residual
-      if (p.relax_uc && (r == 0 || r >= 6)) continue;
-      if (r < 6) row_update_c(rz[r], a[r], p.rho_cpl, beta, lu, rp, rin, zinf, rin_c, y_c);
-      else row_update_c(rz[r], a[r], p.rho_uc, beta, lu, rp, rin, zinf, rin_u, y_u);
-    }
-#pragma unroll
-    for (int r = 0; r < 9; ++r) row_store(rz[r], s.zG + (RG_C1 + r) * TG, s.yG + (RG_C1 + r) * TG, s.lG + (RG_C1 + r) * TG, i, lu);
-    s.ubon[i] = uon;
-    s.ubsu[i] = usu;
-    s.ubsd[i] = usd;
+    cu_rows_item(n, s, p, t, g, i, beta, lu, rp, rin, zinf, rin_c, rin_u, y_c, y_u);
   }
   const double v[3] = {rp, rin, zinf};
   const int which[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
@@ -442,6 +305,14 @@ void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int TN = n.T * n.N;
   if (TN == 0) return;
   hipLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(BLOCK), 0, st, n, s, p);
+}
+
+void launch_bus_fused(const Net& n, const State& s, const Par& p, hipStream_t st, const SlotRanges* fin) {
+  const int nb = n.T * n.N ? bus_blocks(n) : 0;
+  const int nf = fin ? 1 : 0;
+  if (nb + nf == 0) return;
+  const SlotRanges none{};
+  hipLaunchKernelGGL(k_bus_fused, dim3(nf + nb), dim3(BLOCK), 0, st, n, s, p, fin ? *fin : none, nf);
 }
 
 void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st) {

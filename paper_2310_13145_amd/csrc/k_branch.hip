@@ -24,6 +24,7 @@
 #include "ucac_mlp.hpp"
 #include "ucac_units.hpp"
 #include "ucac_ctl.hpp"
+#include "ucac_rows.hpp"
 
 namespace ucac {
 
@@ -671,6 +672,33 @@ k_front(Net n, State s, Par p, int nb_units, int gpb, int fin_units) {
   else branch_body<START, BS>(n, s, p, b - nb_units);
 }
 
+// The first launch of the fused iteration (two launches per iteration; the second,
+// k_bus_fused, solves the bus QP and runs this launch's control step of the iteration
+// before).  With FUSE_PRO every block first finishes the previous iteration's rows
+// it owns: a line block the line ends of its own (line, t) items, lane for lane the
+// items of its Newton solves (bus_post_body); a unit block its generators' rows G1,
+// G2, C1-C6 and U1-U3, with their relaxed commitments committed (unit_rows_body).
+// With FUSE_WORK it then runs this iteration's work on them.  A line lane reads, of
+// what the finish writes, only its own item's rows and duplicates, which it wrote
+// itself; a unit block synchronises between the two parts.  A graph's first launch
+// runs the work alone, its last the finish alone.
+template <int START, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
+k_front_fused(Net n, State s, Par p, int nb_units, int gpb, int mode) {
+  static_assert(BS == BLOCK, "a line block finishes the line ends of its own items");
+  const int b = blockIdx.x;
+  if (b < nb_units) {
+    if (mode & FUSE_PRO) {
+      unit_rows_body<BS>(n, s, p, b, gpb);
+      __syncthreads();
+    }
+    if (mode & FUSE_WORK) unit_body<BS>(n, s, p, b, n.T, gpb);
+  } else {
+    if (mode & FUSE_PRO) bus_post_body(n, s, p, b - nb_units, line_blocks(n));
+    if (mode & FUSE_WORK) branch_body<START, BS>(n, s, p, b - nb_units);
+  }
+}
+
 template <int START, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
 k_front_group(Group gu, Group gb, int grid_u, int slotT, int gpb) {
@@ -771,6 +799,19 @@ void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, in
   else if (p.warm_start == START_PREV)
     hipLaunchKernelGGL((k_front<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb, fin_units);
   else hipLaunchKernelGGL((k_front<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb, fin_units);
+}
+
+void launch_front_fused(const Net& n, const State& s, const Par& p, hipStream_t st, int mode) {
+  const int TL = n.T * n.L;
+  const int gpb = units_gpb(n.T, 16, 256);
+  const int nu = n.G && n.T ? units_blocks(n, gpb) : 0;
+  const int nb = TL ? branch_blocks(n, 256) : 0;
+  if (nu + nb == 0) return;
+  const size_t lds = nu && (mode & FUSE_WORK) ? units_lds(n.T, gpb) : 0;
+  const dim3 grid(nu + nb), block(256);
+  if (p.warm_start == START_PREV)
+    hipLaunchKernelGGL((k_front_fused<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
+  else hipLaunchKernelGGL((k_front_fused<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
 }
 
 template <int BS>

@@ -14,8 +14,14 @@ __global__ void __launch_bounds__(FIN_BLOCK) k_finalize_group(Group gr) {
   finalize_body(M.s, M.p, M.s.red_u);
 }
 
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize_ranges(State s, Par p, SlotRanges R) { finalize_ranges(s, p, R); }
+
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, n, s, p);
+}
+
+void launch_finalize_ranges(const State& s, const Par& p, const SlotRanges& R, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_ranges, dim3(1), dim3(FIN_BLOCK), 0, st, s, p, R);
 }
 
 void launch_finalize_grouped(const Group& g, int grid, hipStream_t st) {

@@ -236,8 +236,11 @@ size_t carve(ucac_handle* h, char* base) {
   s.red_gdual = s.red_bpost + line_blocks(n);
   s.red_n = s.red_gdual + gen_dual_blocks(n);
   s.red_u = s.red_units;
-  s.red = a.take<double>((size_t)(s.red_n + n.G) * NACC);
-  s.redc = a.take<double>((size_t)(s.red_n + n.G) * NCS);
+  s.red_bus2 = s.red_n + n.G;
+  s.red_ugen = s.red_bus2 + bus_blocks(n);
+  s.red_total = s.red_ugen + n.G;
+  s.red = a.take<double>((size_t)s.red_total * NACC);
+  s.redc = a.take<double>((size_t)s.red_total * NCS);
   s.ebuf = a.take<double>(T * 2 * L * 4);
   s.bmu = a.take<double>(2 * T * N);
   s.log_feat = nullptr; s.log_targ = nullptr; s.log_count = nullptr;
@@ -571,6 +574,52 @@ hipError_t enqueue_step_iteration(ucac_handle* h, hipStream_t st, int r, int siz
   return hipSuccess;
 }
 
+// Iteration r of a fused step graph of `size` iterations, two launches per iteration:
+//
+//   A(r) = finish of iteration r-1's rows (r > 0) | iteration r's unit side and lines
+//   B(r) = iteration r's bus solve (without rows G1, G2) | iteration r-1's control step
+//
+// and after the last iteration one launch that finishes its rows, then its control
+// step.  An iteration's residual slots: its unit blocks' (copy r & 1), its bus
+// blocks' (bus copy r & 1), the line-end finish's (red_bpost) and the generator-row
+// finish's (red_ugen), the last two written by the next A; the control step of r - 1
+// thus runs beside the bus solve of r, which writes the other bus copy.  Every
+// iterate is the kernel-by-kernel iteration's bit for bit: the same item arithmetic,
+// each row updated once per iteration after the values it reads, and maxima whose
+// grouping does not change them.  Not with residual balancing (its control step
+// changes penalties the next bus solve reads) nor with the learned start (the
+// network runs before the line kernel, after the line-end finish).
+hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int size, const char** where) {
+  const State& s0 = h->st;
+  const int ucopy[2] = {s0.red_units, s0.red_n};
+  const int bcopy[2] = {s0.red_bus, s0.red_bus2};
+  auto ranges = [&](int k) {
+    const int first[4] = {ucopy[k & 1], bcopy[k & 1], s0.red_bpost, s0.red_ugen};
+    const int count[4] = {s0.red_bus - s0.red_units, bus_blocks(h->net), line_blocks(h->net), h->net.G};
+    return slot_ranges(first, count);
+  };
+  State sr = s0;
+  sr.red_u = ucopy[r & 1];
+  sr.red_bus = bcopy[r & 1];
+  launch_front_fused(h->net, sr, h->kp, st, r > 0 ? FUSE_PRO | FUSE_WORK : FUSE_WORK);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { if (where) *where = "front (fused)"; return e; }
+  const SlotRanges prev = ranges(r - 1);
+  launch_bus_fused(h->net, sr, h->kp, st, r > 0 ? &prev : nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "bus (fused)"; return e; }
+  if (r == size - 1) {
+    launch_front_fused(h->net, sr, h->kp, st, FUSE_PRO);
+    if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "finish (fused)"; return e; }
+    launch_finalize_ranges(sr, h->kp, ranges(r), st);
+    if ((e = hipGetLastError()) != hipSuccess) { if (where) *where = "finalize"; return e; }
+  }
+  return hipSuccess;
+}
+
+// The step graphs' form: fused, unless residual balancing (whose calls run the
+// solve-mode graphs) or the learned start is on; then the pipelined form.
+bool use_fused(const ucac_handle* h) { return h->kp.adapt_every == 0 && h->kp.warm_start != 2; }
+
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
   static const char* names[] = {"units", "branch", "bus", "post", "finalize"};
@@ -593,8 +642,11 @@ int build_graph(ucac_handle* h) {
       const char* where = "";
       hipError_t le = hipSuccess;
       const int size = GRAPH_SIZES[j];
+      const bool fused = !solve && use_fused(h);
       for (int r = 0; r < size && le == hipSuccess; ++r)
-        le = solve ? enqueue_iteration(h, h->own, &where) : enqueue_step_iteration(h, h->own, r, size, &where);
+        le = solve   ? enqueue_iteration(h, h->own, &where)
+             : fused ? enqueue_fused_iteration(h, h->own, r, size, &where)
+                     : enqueue_step_iteration(h, h->own, r, size, &where);
       const hipError_t ce = hipStreamEndCapture(h->own, &gs.g[j]);
       if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
       if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
@@ -776,8 +828,8 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   if (hipMemset(h->st.ub_nxt, 0, sizeof(double) * 3 * T * G) != hipSuccess ||
       hipMemset(h->st.br_iters, 0, sizeof(int) * T * L) != hipSuccess ||
       hipMemset(h->st.br_count, 0, sizeof(unsigned long long) * NBRC * branch_waves(h)) != hipSuccess ||
-      hipMemset(h->st.red, 0, sizeof(double) * NACC * (h->st.red_n + h->net.G)) != hipSuccess ||
-      hipMemset(h->st.redc, 0, sizeof(double) * NCS * (h->st.red_n + h->net.G)) != hipSuccess)
+      hipMemset(h->st.red, 0, sizeof(double) * NACC * h->st.red_total) != hipSuccess ||
+      hipMemset(h->st.redc, 0, sizeof(double) * NCS * h->st.red_total) != hipSuccess)
     return cleanup(fail(h, UCAC_E_DEVICE, "memset failed"));
   h->kp = kernel_params(*params);
   if (set_ctl(h, 0, params->tol) != UCAC_OK) return cleanup(UCAC_E_DEVICE);

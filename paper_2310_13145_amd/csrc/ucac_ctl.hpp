@@ -55,10 +55,40 @@ __device__ inline void adapt_penalties(double* sc, const Par& p, const double (&
   }
 }
 
+// The residual slots of one iteration as up to four contiguous ranges of s.red: flat
+// index b < end[k] (and >= end[k-1]) is slot b + off[k].
+struct SlotRanges {
+  int end[4];
+  int off[4];
+};
+
+__host__ __device__ inline SlotRanges slot_ranges(const int (&first)[4], const int (&count)[4]) {
+  SlotRanges r;
+  int e = 0;
+  for (int k = 0; k < 4; ++k) {
+    r.off[k] = first[k] - e;
+    e += count[k];
+    r.end[k] = e;
+  }
+  return r;
+}
+
+// The kernel-by-kernel and pipelined iterations: the unit side's slots (G of them, from
+// units_slot on, one of its two copies), then every slot from the bus kernel's on.
+__host__ __device__ inline SlotRanges standard_ranges(const State& s, const int units_slot) {
+  const int first[4] = {units_slot, s.red_bus, 0, 0};
+  const int count[4] = {s.red_bus - s.red_units, s.red_n - s.red_bus, 0, 0};
+  return slot_ranges(first, count);
+}
+
+__device__ inline int range_slot(const SlotRanges& R, const int b) {
+  return b + (b < R.end[0] ? R.off[0] : b < R.end[1] ? R.off[1] : b < R.end[2] ? R.off[2] : R.off[3]);
+}
+
 // The control step of one iteration, run by one whole block: reduce every per-block
-// residual slot of the iteration (the unit side's from slot units_slot on), advance the
-// counters and decide (see above).
-__device__ inline void finalize_body(const State& s, const Par& p, const int units_slot) {
+// residual slot of the iteration (the ranges R), advance the counters and decide (see
+// above).
+__device__ inline void finalize_ranges(const State& s, const Par& p, const SlotRanges& R) {
 #pragma clang fp contract(off)
   Ctl* c = s.ctl;
   double* sc = s.sc;
@@ -76,16 +106,15 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
   // up to 8 slots per thread per round, all loads issued before the first use
   double m[NACC] = {0.0, 0.0, 0.0, 0.0};
   constexpr int U = 8;
-  for (int b0 = threadIdx.x; b0 < s.red_n; b0 += U * (int)blockDim.x) {
+  const int nslots = R.end[3];
+  for (int b0 = threadIdx.x; b0 < nslots; b0 += U * (int)blockDim.x) {
     double v[U][NACC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = b0 + u * (int)blockDim.x;
+      const int slot = range_slot(R, b);
 #pragma unroll
-      for (int k = 0; k < NACC; ++k) {
-        const int slot = b < s.red_bus ? units_slot + b : b;
-        v[u][k] = b < s.red_n ? s.red[(size_t)slot * NACC + k] : 0.0;
-      }
+      for (int k = 0; k < NACC; ++k) v[u][k] = b < nslots ? s.red[(size_t)slot * NACC + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -107,8 +136,8 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
 #pragma unroll
   for (int k = 0; k < NCS; ++k) mc[k] = 0.0;
   if (adapt_now) {
-    for (int b = threadIdx.x; b < s.red_n; b += (int)blockDim.x) {
-      const int slot = b < s.red_bus ? units_slot + b : b;
+    for (int b = threadIdx.x; b < nslots; b += (int)blockDim.x) {
+      const int slot = range_slot(R, b);
 #pragma unroll
       for (int k = 0; k < NCS; ++k) mc[k] = nmax(mc[k], s.redc[(size_t)slot * NCS + k]);
     }
@@ -165,5 +194,8 @@ __device__ inline void finalize_body(const State& s, const Par& p, const int uni
   }
 }
 
+__device__ inline void finalize_body(const State& s, const Par& p, const int units_slot) {
+  finalize_ranges(s, p, standard_ranges(s, units_slot));
+}
 
 }  // namespace ucac

@@ -95,13 +95,18 @@ struct State {
   unsigned long long* br_count;  // [waves][NBRC] running totals per wavefront of the line kernel (global lane / 64):
                                  // evaluations, rejected trials, CG its, Newton its, learned-start fallbacks,
                                  // direct Newton steps, projected searches
-  double* red;                   // [red_n][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
-  double* redc;                  // [red_n + G][NCS] the same slots' per-class maxima (residual balancing)
+  double* red;                   // [red_total][NACC] per-block residual maxima of the unit side, bus and post (line ends, then generator rows)
+  double* redc;                  // [red_total][NCS] the same slots' per-class maxima (residual balancing)
   int red_units, red_bus, red_bpost, red_gdual, red_n;  // first slot of each kernel's blocks; total slots
   // The unit side's slots have a second copy at red_n (G slots), so that an iteration's
   // control step can run beside the next iteration's unit blocks: red_u is where this
   // launch's unit blocks write (red_units or red_n).
   int red_u;
+  // The fused iteration's slots: a second copy of the bus kernel's (red_bus2, so that
+  // its control step can run beside the next bus solve; a launch's bus blocks write
+  // from red_bus on, set to either copy) and the unit blocks' finish of the generator
+  // rows (red_ugen, G slots); red_total slots in all.
+  int red_bus2, red_ugen, red_total;
   double* ebuf;                  // [T][2L][4] per line end, in incidence order: P, Q targets, v^2, angle centres
   double* bmu;                   // [2][T][N] balance multipliers of the bus QP
   float* x0;                     // [4][T][L] start points of the learned Newton start (FP32)

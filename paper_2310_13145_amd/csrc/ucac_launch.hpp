@@ -1,6 +1,7 @@
 // Host-side launchers of the iteration kernels (one translation unit each).
 #pragma once
 #include "ucac_dev.hpp"
+#include "ucac_ctl.hpp"
 
 namespace ucac {
 // the unit side (generator update, UC dynamic program, relaxed commitments) per generator
@@ -12,7 +13,8 @@ void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t
 void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st);
-void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);
+void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);  // slots: standard_ranges(s, s.red_u)
+void launch_finalize_ranges(const State& s, const Par& p, const SlotRanges& R, hipStream_t st);
 void launch_lambda(const Net& n, const State& s, const Par& p, hipStream_t st);
 
 // Blocks of each kernel's single-instance grid (what one member contributes to a
@@ -31,6 +33,14 @@ int lambda_blocks(const Net& n);
 // the unit side and the lines in one launch: the units' blocks first, then the lines';
 // with fin_units >= 0 a first block runs the previous iteration's control step
 void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, int fin_units = -1);
+// The fused iteration (two launches): the finish of the previous iteration's rows
+// (mode bit 1) and this iteration's unit side and lines (mode bit 2) in one launch;
+// then the bus solve without rows G1, G2, with the previous iteration's control step
+// over the slot ranges *fin in a first block (none if fin is null).  Flat or
+// previous-iterate Newton start only.
+enum { FUSE_PRO = 1, FUSE_WORK = 2 };
+void launch_front_fused(const Net& n, const State& s, const Par& p, hipStream_t st, int mode);
+void launch_bus_fused(const Net& n, const State& s, const Par& p, hipStream_t st, const SlotRanges* fin);
 void launch_front_grouped(const Group& gu, int grid_u, const Group& gb, int grid_b, int warm_start, int block,
                           int dp_lanes, int max_T, hipStream_t st);
 void launch_bus_grouped(const Group& g, int grid, hipStream_t st);

@@ -327,6 +327,28 @@ def test_kernel_times_same_iterates_as_step():
     assert kt["branch_dispatch"] <= kt["branch"] * 1.001 + 1e-6
 
 
+@pytest.mark.parametrize("name,start", [("mesh118_T24", 0), ("mesh118_T24", 1), ("mesh14_tight_limits", 0),
+                                        ("cfg2", 0)])
+def test_fused_iteration_matches_kernel_by_kernel(name, start):
+    """ucac_step's graphs run the fused iteration (two launches: the previous
+    iteration's row finish with this iteration's unit side and lines, then the bus
+    solve with the previous iteration's control step); its iterates equal the
+    kernel-by-kernel ones bit for bit, across inner-loop ends (max_inner = 3: a pending
+    multiplier update and, where the norm test says so, a new beta every third
+    iteration) and every graph size and call boundary."""
+    inst = synth.config_instance(2) if name == "cfg2" else INSTANCES[name]()
+    print(f"[parity] fused vs kernel-by-kernel {name} start {start}", flush=True)
+    a = ucac.Solver(inst, max_inner=3, warm_start=start)
+    b = ucac.Solver(inst, max_inner=3, warm_start=start)
+    done = 0
+    for n in (1, 5, 16, 70):
+        a.step(n)
+        b.kernel_times(n)
+        done += n
+        np.testing.assert_array_equal(a.get_state(), b.get_state(), err_msg=f"after {done} iterations")
+    assert ucac.split_state(a.get_state(), *dims(inst))["k_outer"] >= 25
+
+
 def test_state_errors():
     inst = synth.config_instance(0)
     g = ucac.Solver(inst)
