@@ -509,23 +509,32 @@ __device__ inline void encode_solution(const Line& L, const double (&x)[4], floa
 
 }  // namespace
 
-// The line subproblem of lane idx: admittances, rating, voltage boxes, line-limit
-// multipliers and the completed-square targets c_r = xbar_r - z_r - y_r / rho_r of
-// its eight rows.  Inactive lanes get a harmless unit line.
-__device__ __forceinline__ Line load_line(const Net& n, const State& s, const Par& p, int idx, bool active) {
+// The line subproblem of lane idx without its targets: admittances, rating, voltage
+// boxes and line-limit multipliers.  Inactive lanes get a harmless unit line.
+__device__ __forceinline__ Line load_line_static(const Net& n, const State& s, const Par& p, int idx, bool active) {
   Line L = {};
   L.rate = 1.0; L.rate2 = 1.0;
   L.rpq = p.rho_pq; L.rva = p.rho_va; L.mu = p.mu; L.inv2mu = 0.5 / p.mu;  // uniform: scalar registers
   if (active) {
-    const int TL = n.T * n.L;
-    const int t = idx / n.L, l = idx - t * n.L;
-    const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
+    const int l = idx % n.L;
     L.G = n.adm[0 * n.L + l]; L.Bs = n.adm[1 * n.L + l]; L.Bm = n.adm[3 * n.L + l];
     L.rate = n.rate[l];
     L.rate2 = L.rate * L.rate;
     L.lo0 = n.vmin[n.from[l]]; L.hi0 = n.vmax[n.from[l]];
     L.lo1 = n.vmin[n.to[l]]; L.hi1 = n.vmax[n.to[l]];
     L.nu0 = s.nuf[idx]; L.nu1 = s.nut[idx];
+  }
+  return L;
+}
+
+// ... and with the completed-square targets c_r = xbar_r - z_r - y_r / rho_r of its
+// eight rows, read from the iterate.
+__device__ __forceinline__ Line load_line(const Net& n, const State& s, const Par& p, int idx, bool active) {
+  Line L = load_line_static(n, s, p, idx, active);
+  if (active) {
+    const int TL = n.T * n.L;
+    const int t = idx / n.L, l = idx - t * n.L;
+    const int bi = t * n.N + n.from[l], bj = t * n.N + n.to[l];
     const double xb[8] = {s.Pbf[idx], s.Qbf[idx], s.Pbt[idx], s.Qbt[idx], s.wb[bi], s.wb[bj], s.thb[bi], s.thb[bj]};
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -536,6 +545,17 @@ __device__ __forceinline__ Line load_line(const Net& n, const State& s, const Pa
   return L;
 }
 
+// ... the targets from the values the line-end finish of the same lane just computed
+// (the values load_line would read back, in the same arithmetic).
+__device__ __forceinline__ void line_targets(Line& L, const LineFinish& f, const Par& p) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double rho = r < 4 ? p.rho_pq : p.rho_va;
+    L.c[r] = f.xb[r] - f.z[r] - f.y[r] / rho;
+  }
+}
+
 // Newton start: START_FLAT (mid-box voltages, zero angles), START_PREV (the line's
 // previous solution) or START_LEARNED: the point k_line_start predicted; a lane whose
 // Newton does not reach the tolerance from there restarts from the flat start (the
@@ -543,17 +563,40 @@ __device__ __forceinline__ Line load_line(const Net& n, const State& s, const Pa
 // free of the others' code and registers.
 enum { START_FLAT = 0, START_PREV = 1, START_LEARNED = 2 };
 
-template <int START, int BS>
+// The LDS save area of a line block's lanes (one per block size, whichever line
+// kernel body instantiation uses it).
+template <int BS>
+__device__ inline GHSave<BS> gh_save_area() {
+  __shared__ double gh_lds[11][BS];
+  return GHSave<BS>{gh_lds};
+}
+
+// FIN (the fused iteration, BS = BLOCK): the lane first finishes the previous
+// iteration's line ends of its own item (line_finish_item, residual maxima to the
+// block's slot red_bpost + blk) and takes its targets from that finish's registers.
+template <int START, int BS, bool FIN = false>
 __device__ __forceinline__ void branch_body(const Net& n, const State& s, const Par& p0, const int blk) {
   if (s.ctl->halt) return;
   const Par p = live_par(p0, s);
-  __shared__ double gh_lds[11][BS];
-  const GHSave<BS> save{gh_lds};
+  const GHSave<BS> save = gh_save_area<BS>();
   const int TL = n.T * n.L;
   const int idx = blk * BS + threadIdx.x;
   const bool active = idx < TL;
   int n_eval = 0, n_rej = 0, n_cg = 0, it = 0, n_fb = 0, n_dir = 0, n_srch = 0;
-  const Line L = load_line(n, s, p, idx, active);
+  Line L;
+  if (FIN) {
+    static_assert(!FIN || BS == BLOCK, "the finish's block slots are per BLOCK items");
+    L = load_line_static(n, s, p, idx, active);
+    double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    if (active) {
+      LineFinish f;
+      line_finish_item(n, s, p, idx, s.sc[SC_BETA], lambda_pending(s, p), rp, rin, rd, zinf, c0, c1, c2, c3, &f);
+      line_targets(L, f, p);
+    }
+    line_finish_store(s, p, blk, rp, rin, rd, zinf, c0, c1, c2, c3);
+  } else {
+    L = load_line(n, s, p, idx, active);
+  }
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
   double x[4];
@@ -693,9 +736,12 @@ k_front_fused(Net n, State s, Par p, int nb_units, int gpb, int mode) {
       __syncthreads();
     }
     if (mode & FUSE_WORK) unit_body<BS>(n, s, p, b, n.T, gpb);
+  } else if (mode == (FUSE_PRO | FUSE_WORK)) {
+    branch_body<START, BS, true>(n, s, p, b - nb_units);
+  } else if (mode == FUSE_PRO) {
+    bus_post_body(n, s, p, b - nb_units, line_blocks(n));
   } else {
-    if (mode & FUSE_PRO) bus_post_body(n, s, p, b - nb_units, line_blocks(n));
-    if (mode & FUSE_WORK) branch_body<START, BS>(n, s, p, b - nb_units);
+    branch_body<START, BS>(n, s, p, b - nb_units);
   }
 }
 

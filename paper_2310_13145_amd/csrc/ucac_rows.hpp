@@ -144,56 +144,74 @@ __device__ inline void g12_rows_item(const State& s, const Par& p, const int TG,
   row_store(r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, i, lu);
 }
 
-// Rows z, y of both ends of line item idx = t * L + l from the bus solve (the line-end
-// finish of step:opf_bar: Pbar, Qbar from the end buses' balance multipliers, then the
-// eight line rows); residual maxima to slot red_bpost + blk.
-__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
+// What the line-end finish of one item computes, for a caller that goes on with the
+// item (the fused iteration's line lane), by line row (Pf Qf Pt Qt Wf Wt Thf Tht):
+// the bus-side values the rows compare with (the new Pbar, Qbar of both ends, the end
+// buses' wbar and thetabar) and the rows' new z and y.
+struct LineFinish {
+  double xb[NRB], z[NRB], y[NRB];
+};
+
+// The line-end finish of line item idx = t * L + l (step:opf_bar's Pbar, Qbar of both
+// ends from the end buses' balance multipliers, then z, y of the line's eight rows),
+// accumulating the residual maxima; with out set, also what LineFinish holds.
+__device__ inline void line_finish_item(const Net& n, const State& s, const Par& p, const int idx, const double beta,
+                                        const LamUpd& lu, double& rp, double& rin, double& rd, double& zinf,
+                                        double& rin_pq, double& rin_va, double& y_pq, double& y_va,
+                                        LineFinish* out) {
 #pragma clang fp contract(off)
-  if (s.ctl->halt) return;
-  const Par p = live_par(p0, s);
   const int TL = n.T * n.L, TN = n.T * n.N;
-  const int idx = blk * BLOCK + threadIdx.x;
-  double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
-  double rin_pq = 0.0, rin_va = 0.0, y_pq = 0.0, y_va = 0.0;  // class maxima
-  if (idx < TL) {
-    const int t = idx / n.L, l = idx - t * n.L;
-    const double rpq = p.rho_pq, rva = p.rho_va;
-    const double beta = s.sc[SC_BETA];
-    const LamUpd lu = lambda_pending(s, p);
-    // every load of both ends first, then the updates, then the stores
-    EndData d[2];
-    double mu1[2], mu2[2], wnew[2], thnew[2], Pold[2], Qold[2];
-    RowZY r[2][4];
+  const int t = idx / n.L, l = idx - t * n.L;
+  const double rpq = p.rho_pq, rva = p.rho_va;
+  // every load of both ends first, then the updates, then the stores
+  EndData d[2];
+  double mu1[2], mu2[2], wnew[2], thnew[2], Pold[2], Qold[2];
+  RowZY r[2][4];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      d[side] = load_end(n, s, t, TL, 2 * l + side, rpq);
-      const int b = t * n.N + (side ? n.to[l] : n.from[l]);
-      mu1[side] = s.bmu[b]; mu2[side] = s.bmu[TN + b]; wnew[side] = s.wb[b]; thnew[side] = s.thb[b];
-      const int k = d[side].k;
-      Pold[side] = side ? s.Pbt[k] : s.Pbf[k];
-      Qold[side] = side ? s.Qbt[k] : s.Qbf[k];
-      const int rows[4] = {d[side].rP, d[side].rQ, d[side].rW, d[side].rT};
+  for (int side = 0; side < 2; ++side) {
+    d[side] = load_end(n, s, t, TL, 2 * l + side, rpq);
+    const int b = t * n.N + (side ? n.to[l] : n.from[l]);
+    mu1[side] = s.bmu[b]; mu2[side] = s.bmu[TN + b]; wnew[side] = s.wb[b]; thnew[side] = s.thb[b];
+    const int k = d[side].k;
+    Pold[side] = side ? s.Pbt[k] : s.Pbf[k];
+    Qold[side] = side ? s.Qbt[k] : s.Qbf[k];
+    const int rows[4] = {d[side].rP, d[side].rQ, d[side].rW, d[side].rT};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) r[side][q] = row_load(s.zB + rows[q] * TL, s.yB + rows[q] * TL, s.lB + rows[q] * TL, k);
-    }
+    for (int q = 0; q < 4; ++q) r[side][q] = row_load(s.zB + rows[q] * TL, s.yB + rows[q] * TL, s.lB + rows[q] * TL, k);
+  }
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const EndData& q = d[side];
-      const double Pn = q.tP - mu1[side] / rpq, Qn = q.tQ - mu2[side] / rpq;
-      rd = nmax(rd, nmax(fabs(Pn - Pold[side]), fabs(Qn - Qold[side])));
-      row_update_c(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
-      row_update_c(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
-      row_update_c(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
-      row_update_c(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
-      double* Pdup = side ? s.Pbt : s.Pbf;
-      double* Qdup = side ? s.Qbt : s.Qbf;
-      Pdup[q.k] = Pn;
-      Qdup[q.k] = Qn;
-      const int rows[4] = {q.rP, q.rQ, q.rW, q.rT};
+  for (int side = 0; side < 2; ++side) {
+    const EndData& q = d[side];
+    const double Pn = q.tP - mu1[side] / rpq, Qn = q.tQ - mu2[side] / rpq;
+    rd = nmax(rd, nmax(fabs(Pn - Pold[side]), fabs(Qn - Qold[side])));
+    row_update_c(r[side][0], q.fP - Pn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+    row_update_c(r[side][1], q.fQ - Qn, rpq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+    row_update_c(r[side][2], q.v * q.v - wnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
+    row_update_c(r[side][3], q.th - thnew[side], rva, beta, lu, rp, rin, zinf, rin_va, y_va);
+    double* Pdup = side ? s.Pbt : s.Pbf;
+    double* Qdup = side ? s.Qbt : s.Qbf;
+    Pdup[q.k] = Pn;
+    Qdup[q.k] = Qn;
+    const int rows[4] = {q.rP, q.rQ, q.rW, q.rT};
 #pragma unroll
-      for (int w = 0; w < 4; ++w) row_store(r[side][w], s.zB + rows[w] * TL, s.yB + rows[w] * TL, s.lB + rows[w] * TL, q.k, lu);
+    for (int w = 0; w < 4; ++w) row_store(r[side][w], s.zB + rows[w] * TL, s.yB + rows[w] * TL, s.lB + rows[w] * TL, q.k, lu);
+    if (out) {
+      const double xb[4] = {Pn, Qn, wnew[side], thnew[side]};
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        out->xb[rows[w]] = xb[w];
+        out->z[rows[w]] = r[side][w].z;
+        out->y[rows[w]] = r[side][w].y;
+      }
     }
   }
+}
+
+// Residual maxima of a block's line-end finish to slot red_bpost + blk (every thread
+// of the block calls it).
+__device__ inline void line_finish_store(const State& s, const Par& p, const int blk, const double rp, const double rin,
+                                         const double rd, const double zinf, const double rin_pq, const double rin_va,
+                                         const double y_pq, const double y_va) {
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bpost + blk) * NACC);
@@ -203,6 +221,21 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
     const int wc[5] = {CS_RIN + CL_PQ, CS_RIN + CL_VA, CS_Y + CL_PQ, CS_Y + CL_VA, CS_DX + CL_PQ};
     block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bpost + blk) * NCS);
   }
+}
+
+// The line-end finish of the items of block blk (one lane per (line, t)).
+__device__ __forceinline__ void bus_post_body(const Net& n, const State& s, const Par& p0, const int blk, const int nblk) {
+  if (s.ctl->halt) return;
+  const Par p = live_par(p0, s);
+  const int idx = blk * BLOCK + threadIdx.x;
+  double rp = 0.0, rin = 0.0, rd = 0.0, zinf = 0.0;
+  double rin_pq = 0.0, rin_va = 0.0, y_pq = 0.0, y_va = 0.0;  // class maxima
+  if (idx < n.T * n.L) {
+    const double beta = s.sc[SC_BETA];
+    const LamUpd lu = lambda_pending(s, p);
+    line_finish_item(n, s, p, idx, beta, lu, rp, rin, rd, zinf, rin_pq, rin_va, y_pq, y_va, nullptr);
+  }
+  line_finish_store(s, p, blk, rp, rin, rd, zinf, rin_pq, rin_va, y_pq, y_va);
 }
 
 // The previous iteration's generator rows, finished by the unit block that owns the
