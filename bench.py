@@ -95,6 +95,39 @@ def branch_traffic():
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 
 
+def line_roofline(solver, inst, from_iter):
+    """The line kernel's roofline from the solver's current iterate: one untimed
+    kernel-by-kernel iteration (every kernel's first launch in the process), then
+    PROF_ITERS timed ones from the same iterate; algorithmic flops from the device work
+    counters over the dispatch-timestamp mean.  Returns it and the kernel means."""
+    state = solver.get_state()
+    solver.kernel_times(1)
+    solver.set_state(state)
+    solver.branch_counters(reset=True)
+    ktimes = solver.kernel_times(PROF_ITERS)
+    cnt = solver.branch_counters(reset=True)
+    branch_dispatch_ms = ktimes.pop("branch_dispatch")
+    lanes = inst["T"] * inst["n_line"]
+    # the kernel evaluates value, gradient and Hessian at the start and at every trial
+    # point; the method needs the full evaluation at the start and at accepted points and
+    # only the value at rejected ones, which is what is counted
+    full = cnt["evals"] - cnt["rejected"]
+    flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
+                        cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON +
+                        cnt["searches"] * FLOP_SEARCH) / PROF_ITERS + lanes * FLOP_LANE
+    achieved = flops_per_launch / (branch_dispatch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "branch (trust-region Newton, one lane per line-period)",
+            "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "flops_per_launch": flops_per_launch, "launch_ms": branch_dispatch_ms,
+            "launch_ms_between_events": ktimes["branch"], "line_solves_per_launch": lanes,
+            "newton_iters_per_solve": cnt["newton"] / PROF_ITERS / lanes,
+            "projected_searches_per_launch": cnt["searches"] / PROF_ITERS,
+            "profiled_iterations": f"{PROF_ITERS} kernel-by-kernel iterations from the iterate after "
+                                   f"{from_iter}, after one untimed iteration"}
+    return roof, ktimes
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +149,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-dp", action="store_true", help="skip the standalone DP benchmark")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the line-kernel roofline on the 10,000-bus T = 48 workload")
     ap.add_argument("--hbm-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (reads and writes exactly 1 GiB per "
                          "dispatch), the known-size kernel the HBM byte counters are scaled by")
@@ -430,24 +465,10 @@ def main():
     # taken from its dispatch timestamps, what a kernel trace of the same run reports
     solver.set_state(state0)
     solver.step(max(0, PROF_FROM - args.warmup))
-    state_prof = solver.get_state()
-    solver.kernel_times(1)
-    solver.set_state(state_prof)
-    solver.branch_counters(reset=True)
-    ktimes = solver.kernel_times(PROF_ITERS)
-    cnt = solver.branch_counters(reset=True)
-    branch_dispatch_ms = ktimes.pop("branch_dispatch")
+    roof, ktimes = line_roofline(solver, inst, max(PROF_FROM, args.warmup))
+    roof["traffic"] = branch_traffic()
     prof_ms_per_step = sum(ktimes.values())
     lanes = T * L
-    # the kernel evaluates value, gradient and Hessian at the start and at every trial
-    # point; the method needs the full evaluation at the start and at accepted points and
-    # only the value at rejected ones, which is what is counted
-    full = cnt["evals"] - cnt["rejected"]
-    flops_per_launch = (full * FLOP_EVAL + cnt["rejected"] * FLOP_TRIAL + cnt["cg"] * FLOP_CG +
-                        cnt["direct"] * FLOP_DIRECT + cnt["newton"] * FLOP_NEWTON +
-                        cnt["searches"] * FLOP_SEARCH) / PROF_ITERS + lanes * FLOP_LANE
-    br_s = branch_dispatch_ms * 1e-3
-    achieved = flops_per_launch / br_s / 1e12
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
     hbm = {
         "post": {"bytes": lanes * BYTES_BUS_POST + G * T * BYTES_GEN_DUAL, "ms": ktimes["post"]},
@@ -474,20 +495,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n_bus": N, "n_line": L, "n_gen": G, "T": T,
                    "branch_solves_per_step": lanes, "newton_start": "flat (plain method)"},
-        "roofline": {"bound": "alu", "kernel": "branch (trust-region Newton, one lane per line-period)",
-                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": branch_traffic(),
-                     "flops_per_launch": flops_per_launch, "launch_ms": branch_dispatch_ms,
-                     "launch_ms_between_events": ktimes["branch"],
-                     "newton_iters_per_solve": cnt["newton"] / PROF_ITERS / lanes,
-                     "projected_searches_per_launch": cnt["searches"] / PROF_ITERS,
-                     "profiled_iterations": f"{PROF_ITERS} kernel-by-kernel iterations from the iterate after "
-                                            f"{max(PROF_FROM, args.warmup)}, after one untimed iteration"},
+        "roofline": roof,
         "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps},
         "kernels_ms": ktimes,
         "profiled_ms_per_step": prof_ms_per_step,
         "hbm": hbm,
     }
+
+    if not args.no_large:
+        # the same line-kernel roofline on the 10,000-bus T = 48 workload (624,000 line
+        # solves per launch, several waves per SIMD): from its iterate after PROF_FROM
+        # iterations, PROF_ITERS kernel-by-kernel iterations
+        big = synth.config_instance(4)
+        s4 = ucac.Solver(big)
+        s4.step(PROF_FROM)
+        out["roofline_" + synth.CONFIGS[4]["name"]], _ = line_roofline(s4, big, PROF_FROM)
+        s4.close()
 
     if not args.no_solve:
         out["time_to_tol"] = time_to_tol(ucac, torch, inst, args)

@@ -556,6 +556,19 @@ __device__ __forceinline__ void line_targets(Line& L, const LineFinish& f, const
   }
 }
 
+// The learned start of a lane of the fused launch: the network on its line data
+// (every lane of the wavefront calls it: wavefront barriers inside), decoded to
+// (v_i, v_j, th_i, th_j) in FP32 as k_line_start stores them in x0.
+__device__ inline void learned_start_point(const Line& L, const Par& p, __bf16* buf, float (&x0)[4]) {
+  float f[MLP_IN], y[MLP_OUT];
+  line_features(L, f);
+  mlp_forward_layers(p.mlp, f, buf, y);
+  x0[0] = 1.0f + y[0];
+  x0[1] = 1.0f + y[1];
+  x0[2] = (float)(L.c[6] + 0.1 * (double)y[2]);
+  x0[3] = (float)(L.c[7] + 0.1 * (double)y[3]);
+}
+
 // Newton start: START_FLAT (mid-box voltages, zero angles), START_PREV (the line's
 // previous solution) or START_LEARNED: the point k_line_start predicted; a lane whose
 // Newton does not reach the tolerance from there restarts from the flat start (the
@@ -600,7 +613,22 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   const double lo[4] = {L.lo0, L.lo1, -TWO_PI, -TWO_PI};
   const double hi[4] = {L.hi0, L.hi1, TWO_PI, TWO_PI};
   double x[4];
-  if (START == START_LEARNED && active) {
+  if (START == START_LEARNED && FIN) {
+    // the network on the targets the finish just formed (what k_line_start computes
+    // from them after reading them back), its LDS in the launch's dynamic area
+    extern __shared__ __bf16 lds_net[];
+    float x0[4];
+    learned_start_point(L, p, lds_net + (threadIdx.x >> 6) * MLP_WAVE_LDS, x0);
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s.x0[k * TL + idx] = x0[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = (double)x0[k];
+    if (!(x[0] == x[0] && x[1] == x[1] && x[2] == x[2] && x[3] == x[3])) {
+      x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
+    }
+  } else if (START == START_LEARNED && active) {
     // the point k_line_start predicted for this line (FP32), NaN-guarded
     x[0] = (double)s.x0[idx]; x[1] = (double)s.x0[TL + idx];
     x[2] = (double)s.x0[2 * TL + idx]; x[3] = (double)s.x0[3 * TL + idx];
@@ -614,11 +642,12 @@ __device__ __forceinline__ void branch_body(const Net& n, const State& s, const 
   }
   if (active) {
     bool conv;
-    it = newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
-    if (START == START_LEARNED && !conv) {
+    it = 0;
+    for (int attempt = 0;; ++attempt) {
+      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
+      if (START != START_LEARNED || conv || attempt) break;
       ++n_fb;
       x[0] = 0.5 * (L.lo0 + L.hi0); x[1] = 0.5 * (L.lo1 + L.hi1); x[2] = 0.0; x[3] = 0.0;
-      it += newton<BS>(L, lo, hi, x, p, save, n_eval, n_rej, n_cg, n_dir, n_srch, conv);
     }
     // z, y of the eight rows for the per-end sums below, loaded before this lane's
     // first store so that their latency overlaps the final flows
@@ -738,10 +767,11 @@ k_front_fused(Net n, State s, Par p, int nb_units, int gpb, int mode) {
     if (mode & FUSE_WORK) unit_body<BS>(n, s, p, b, n.T, gpb);
   } else if (mode == (FUSE_PRO | FUSE_WORK)) {
     branch_body<START, BS, true>(n, s, p, b - nb_units);
-  } else if (mode == FUSE_PRO) {
-    bus_post_body(n, s, p, b - nb_units, line_blocks(n));
-  } else {
-    branch_body<START, BS>(n, s, p, b - nb_units);
+  } else if constexpr (START != START_LEARNED) {
+    // (the learned start's first and last launches of a graph use the other kernels:
+    // its instantiation keeps only the finish-and-solve path, and its registers)
+    if (mode == FUSE_PRO) bus_post_body(n, s, p, b - nb_units, line_blocks(n));
+    else branch_body<START, BS>(n, s, p, b - nb_units);
   }
 }
 
@@ -766,8 +796,7 @@ k_front_group(Group gu, Group gb, int grid_u, int slotT, int gpb) {
 // (v_i, v_j, th_i, th_j) as FP32 in x0 [4][T*L].  A kernel of its own so that the
 // Newton kernel keeps its registers (no spills) and the network runs at the
 // occupancy its small footprint allows.
-// One wavefront per block: the forward pass's block barriers then wait for no other
-// wavefront, and the launch spreads over every CU.
+// One wavefront per block, so that the launch spreads over every CU.
 constexpr int START_BLOCK = 64;
 
 __global__ void __launch_bounds__(START_BLOCK) k_line_start(Net n, State s, Par p0) {
@@ -853,9 +882,22 @@ void launch_front_fused(const Net& n, const State& s, const Par& p, hipStream_t 
   const int nu = n.G && n.T ? units_blocks(n, gpb) : 0;
   const int nb = TL ? branch_blocks(n, 256) : 0;
   if (nu + nb == 0) return;
-  const size_t lds = nu && (mode & FUSE_WORK) ? units_lds(n.T, gpb) : 0;
+  size_t lds = nu && (mode & FUSE_WORK) ? units_lds(n.T, gpb) : 0;
   const dim3 grid(nu + nb), block(256);
-  if (p.warm_start == START_PREV)
+  if (p.warm_start == START_LEARNED) {
+    // with the finish, the line blocks evaluate the network in the launch's dynamic
+    // LDS (beside the unit blocks' DP tables); without it (a graph's first launch),
+    // the network kernel runs first, as in the other forms
+    if (mode == (FUSE_PRO | FUSE_WORK)) {
+      const size_t net = sizeof(__bf16) * MLP_WAVE_LDS * (256 / 64);
+      lds = lds > net ? lds : net;
+      hipLaunchKernelGGL((k_front_fused<START_LEARNED, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
+    } else if (mode == FUSE_WORK) {
+      launch_front(n, s, p, st, -1);  // the network kernel, then the unit side and lines
+    } else {
+      hipLaunchKernelGGL((k_front_fused<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
+    }
+  } else if (p.warm_start == START_PREV)
     hipLaunchKernelGGL((k_front_fused<START_PREV, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
   else hipLaunchKernelGGL((k_front_fused<START_FLAT, 256>), grid, block, lds, st, n, s, p, nu, gpb, mode);
 }

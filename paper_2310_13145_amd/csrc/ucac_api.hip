@@ -81,6 +81,7 @@ struct ucac_handle {
   GraphSet graphs_solve;  // solve mode: GRAPH_SIZES[j] iterations, each with its own control-step kernel
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
+  int cus = 0;               // compute units of the device
   std::vector<double> cold;  // the cold-start iterate (internal layout)
   // learned warm start: FP32 parameters and BF16 operand copies
   void* mlp_mem = nullptr;
@@ -587,8 +588,8 @@ hipError_t enqueue_step_iteration(ucac_handle* h, hipStream_t st, int r, int siz
 // iterate is the kernel-by-kernel iteration's bit for bit: the same item arithmetic,
 // each row updated once per iteration after the values it reads, and maxima whose
 // grouping does not change them.  Not with residual balancing (its control step
-// changes penalties the next bus solve reads) nor with the learned start (the
-// network runs before the line kernel, after the line-end finish).
+// changes penalties the next bus solve reads).  With the learned start the line lanes
+// evaluate the network between the finish and the Newton solve.
 hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int size, const char** where) {
   const State& s0 = h->st;
   const int ucopy[2] = {s0.red_units, s0.red_n};
@@ -616,9 +617,23 @@ hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int si
   return hipSuccess;
 }
 
-// The step graphs' form: fused, unless residual balancing (whose calls run the
-// solve-mode graphs) or the learned start is on; then the pipelined form.
-bool use_fused(const ucac_handle* h) { return h->kp.adapt_every == 0 && h->kp.warm_start != 2; }
+// The step graphs' form: fused, unless residual balancing is on (its calls run the
+// solve-mode graphs) or the learned start's network would hold back a launch of
+// several rounds of wavefronts; then the pipelined form.  Inside the fused launch
+// the network saves a kernel and the reads of its inputs, which pays where the whole
+// launch is resident at once (its time is the slowest lane's latency); its registers
+// there lower what the line kernel's lanes may hold, which costs more where they
+// queue for the CUs, and there the network kernel runs at its own occupancy (measured
+// at 76,800 and 624,000 line solves: 0.96x and 0.92x of the plain iteration in the
+// fused launch, 0.92x and 0.99x as a kernel of its own).
+bool use_fused(const ucac_handle* h) {
+  if (h->kp.adapt_every > 0) return false;
+  if (h->kp.warm_start != 2) return true;
+  const int gpb = units_gpb(h->T, 16, 256);
+  const long waves = 4L * ((h->G && h->T ? units_blocks(h->net, gpb) : 0) +
+                           (h->T * h->L ? branch_blocks(h->net, 256) : 0));
+  return waves <= 8L * h->cus;  // two 256-thread blocks per CU
+}
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
@@ -730,6 +745,8 @@ int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle*
   net = &perm.view;
   h->N = net->n_bus; h->L = net->n_line; h->G = net->n_gen; h->T = net->T; h->ref = net->ref_bus;
   h->par = *params;
+  if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, params->device) != hipSuccess || h->cus < 1)
+    h->cus = 1;
   const size_t N = h->N, L = h->L, G = h->G, T = h->T;
   h->n_state = state_doubles(N, L, G, T);
 

@@ -36,8 +36,7 @@ void launch_front(const Net& n, const State& s, const Par& p, hipStream_t st, in
 // The fused iteration (two launches): the finish of the previous iteration's rows
 // (mode bit 1) and this iteration's unit side and lines (mode bit 2) in one launch;
 // then the bus solve without rows G1, G2, with the previous iteration's control step
-// over the slot ranges *fin in a first block (none if fin is null).  Flat or
-// previous-iterate Newton start only.
+// over the slot ranges *fin in a first block (none if fin is null).
 enum { FUSE_PRO = 1, FUSE_WORK = 2 };
 void launch_front_fused(const Net& n, const State& s, const Par& p, hipStream_t st, int mode);
 void launch_bus_fused(const Net& n, const State& s, const Par& p, hipStream_t st, const SlotRanges* fin);

@@ -35,6 +35,23 @@ __device__ inline float dsilu_f(float z) {
 
 __device__ inline bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
+// Orders a wavefront's LDS accesses across its lanes where the buffer is private to the
+// wavefront: the hardware performs a wavefront's LDS operations in program order, so
+// only the compiler has to be kept from moving them across this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The barrier of the forward pass: the block's (every lane of the block calls the
+// pass) or, with WAVE, the wavefront's (every lane of the wavefront calls it).
+template <bool WAVE>
+__device__ inline void mlp_sync() {
+  if (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 __device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
 
 __device__ inline int d_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
@@ -79,7 +96,7 @@ __device__ inline void mlp_load_frags(const Mlp& w, MlpFrags& f) {
 // Each 32-sample tile is read completely before it is overwritten; the block
 // barriers order the reads of every lane before the writes, so every lane of the
 // block calls this.
-template <int K, int NOUT>
+template <int K, int NOUT, bool WAVE = false>
 __device__ inline void layer_silu_inplace(__bf16* X, const bf16x8 (&A)[NOUT / 32][K / 16],
                                           const float (&bias)[NOUT / 32][4][4]) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
@@ -92,7 +109,7 @@ __device__ inline void layer_silu_inplace(__bf16* X, const bf16x8 (&A)[NOUT / 32
 #pragma unroll
       for (int ks = 0; ks < K / 16; ++ks) acc[to] = mfma(A[to][ks], ld8(X + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[to]);
     }
-    __syncthreads();
+    mlp_sync<WAVE>();
     __bf16* row = X + (ts * 32 + r) * MLP_LD;
 #pragma unroll
     for (int to = 0; to < NOUT / 32; ++to)
@@ -105,7 +122,7 @@ __device__ inline void layer_silu_inplace(__bf16* X, const bf16x8 (&A)[NOUT / 32
         for (int q = 0; q < 4; ++q) v[q] = (__bf16)silu_fast(acc[to][4 * jb + q] + bias[to][jb][q]);
         *reinterpret_cast<bf16x4*>(row + o) = v;
       }
-    __syncthreads();
+    mlp_sync<WAVE>();
   }
 }
 
@@ -151,6 +168,77 @@ __device__ inline void mlp_forward_frags(const MlpFrags& fr, const float* b3, co
 #pragma unroll
   for (int o = 0; o < MLP_OUT; ++o) out[o] = Yf[lane * MLP_OUT + o];
   __syncthreads();
+}
+
+// The same arithmetic for a caller that keeps other work live (the fused line lanes):
+// each layer's operands loaded just before the layer (a third of the registers of
+// mlp_forward_frags) and wavefront barriers (the buffer is the wavefront's own), so
+// that every lane of the wavefront calls it.
+__device__ inline void mlp_forward_layers(const Mlp& w, const float (&feat)[MLP_IN], __bf16* buf, float (&out)[MLP_OUT]) {
+  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    __bf16* row = buf + lane * MLP_LD;
+#pragma unroll
+    for (int k = 0; k < MLP_KIN; k += 4) {
+      bf16x4 v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = (__bf16)(k + q < MLP_IN ? feat[k + q] : 0.0f);
+      *reinterpret_cast<bf16x4*>(row + k) = v;
+    }
+  }
+  wave_sync();
+  {
+    bf16x8 a[MLP_H / 32][MLP_KIN / 16];
+    float b[MLP_H / 32][4][4];
+#pragma unroll
+    for (int to = 0; to < MLP_H / 32; ++to) {
+#pragma unroll
+      for (int ks = 0; ks < MLP_KIN / 16; ++ks) a[to][ks] = ld8(w.W1b + (to * 32 + r) * MLP_KIN + ks * 16 + h * 8);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[to][jb][q] = w.b1[to * 32 + 8 * jb + 4 * h + q];
+    }
+    layer_silu_inplace<MLP_KIN, MLP_H, true>(buf, a, b);
+  }
+  {
+    bf16x8 a[MLP_H / 32][MLP_H / 16];
+    float b[MLP_H / 32][4][4];
+#pragma unroll
+    for (int to = 0; to < MLP_H / 32; ++to) {
+#pragma unroll
+      for (int ks = 0; ks < MLP_H / 16; ++ks) a[to][ks] = ld8(w.W2b + (to * 32 + r) * MLP_H + ks * 16 + h * 8);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[to][jb][q] = w.b2[to * 32 + 8 * jb + 4 * h + q];
+    }
+    layer_silu_inplace<MLP_H, MLP_H, true>(buf, a, b);
+  }
+  bf16x8 a3[MLP_H / 16];
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks) a3[ks] = ld8(w.W3b + r * MLP_H + ks * 16 + h * 8);
+  // output layer as in mlp_forward_frags
+  f32x16 acc[2];
+#pragma unroll
+  for (int ts = 0; ts < 2; ++ts) {
+    acc[ts] = f32x16{};
+#pragma unroll
+    for (int ks = 0; ks < MLP_H / 16; ++ks) acc[ts] = mfma(a3[ks], ld8(buf + (ts * 32 + r) * MLP_LD + ks * 16 + h * 8), acc[ts]);
+  }
+  wave_sync();
+  float* Yf = reinterpret_cast<float*>(buf);
+  if (h == 0) {
+#pragma unroll
+    for (int ts = 0; ts < 2; ++ts)
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) Yf[(ts * 32 + r) * MLP_OUT + o] = acc[ts][o] + w.b3[o];
+  }
+  wave_sync();
+#pragma unroll
+  for (int o = 0; o < MLP_OUT; ++o) out[o] = Yf[lane * MLP_OUT + o];
+  wave_sync();
 }
 
 __device__ inline void mlp_forward_wave(const Mlp& w, const float (&feat)[MLP_IN], __bf16* buf, float (&out)[MLP_OUT]) {

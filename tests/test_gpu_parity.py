@@ -328,24 +328,35 @@ def test_kernel_times_same_iterates_as_step():
 
 
 @pytest.mark.parametrize("name,start", [("mesh118_T24", 0), ("mesh118_T24", 1), ("mesh14_tight_limits", 0),
-                                        ("cfg2", 0)])
-def test_fused_iteration_matches_kernel_by_kernel(name, start):
+                                        ("cfg2", 0), ("mesh118_T24", 2), ("cfg2", 2), ("cfg4", 2)])
+def test_step_graphs_match_kernel_by_kernel(name, start):
     """ucac_step's graphs run the fused iteration (two launches: the previous
     iteration's row finish with this iteration's unit side and lines, then the bus
     solve with the previous iteration's control step); its iterates equal the
     kernel-by-kernel ones bit for bit, across inner-loop ends (max_inner = 3: a pending
     multiplier update and, where the norm test says so, a new beta every third
-    iteration) and every graph size and call boundary."""
-    inst = synth.config_instance(2) if name == "cfg2" else INSTANCES[name]()
+    iteration) and every graph size and call boundary.  Start 2: the learned start (an
+    untrained network), evaluated inside the fused launch's line lanes (118 and 2,000
+    buses) or, at 10,000 buses, in the network kernel of the pipelined form, against
+    the network kernel before the line kernel; the start points too are equal."""
+    inst = synth.config_instance({"cfg2": 2, "cfg4": 4}[name]) if name.startswith("cfg") else INSTANCES[name]()
     print(f"[parity] fused vs kernel-by-kernel {name} start {start}", flush=True)
-    a = ucac.Solver(inst, max_inner=3, warm_start=start)
-    b = ucac.Solver(inst, max_inner=3, warm_start=start)
+    a = ucac.Solver(inst, max_inner=3, warm_start=min(start, 1))
+    b = ucac.Solver(inst, max_inner=3, warm_start=min(start, 1))
+    if start == 2:
+        net = ucac.WarmStartNet(seed=8)
+        w = net.get_weights()
+        net.close()
+        a.set_warmstart(w)
+        b.set_warmstart(w)
     done = 0
     for n in (1, 5, 16, 70):
         a.step(n)
         b.kernel_times(n)
         done += n
         np.testing.assert_array_equal(a.get_state(), b.get_state(), err_msg=f"after {done} iterations")
+        if start == 2:
+            np.testing.assert_array_equal(a.line_starts(), b.line_starts(), err_msg=f"start points, {done}")
     assert ucac.split_state(a.get_state(), *dims(inst))["k_outer"] >= 25
 
 
