@@ -617,6 +617,14 @@ hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int si
   return hipSuccess;
 }
 
+// Wavefronts of the launch that runs the unit side and the lines (256-thread blocks),
+// against what the CUs hold at once (two such blocks per CU).
+bool front_queues(const ucac_handle* h) {
+  const long unit_blocks = h->G && h->T ? (h->G + units_gpb(h->T, 16, 256) - 1) / units_gpb(h->T, 16, 256) : 0;
+  const long line_blocks = ((long)h->T * h->L + 255) / 256;
+  return 4L * (unit_blocks + line_blocks) > 8L * h->cus;
+}
+
 // The step graphs' form: fused, unless residual balancing is on (its calls run the
 // solve-mode graphs) or the learned start's network would hold back a launch of
 // several rounds of wavefronts; then the pipelined form.  Inside the fused launch
@@ -628,11 +636,7 @@ hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int si
 // fused launch, 0.92x and 0.99x as a kernel of its own).
 bool use_fused(const ucac_handle* h) {
   if (h->kp.adapt_every > 0) return false;
-  if (h->kp.warm_start != 2) return true;
-  const int gpb = units_gpb(h->T, 16, 256);
-  const long waves = 4L * ((h->G && h->T ? units_blocks(h->net, gpb) : 0) +
-                           (h->T * h->L ? branch_blocks(h->net, 256) : 0));
-  return waves <= 8L * h->cus;  // two 256-thread blocks per CU
+  return h->kp.warm_start != 2 || !front_queues(h);
 }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).

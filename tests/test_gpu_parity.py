@@ -328,7 +328,7 @@ def test_kernel_times_same_iterates_as_step():
 
 
 @pytest.mark.parametrize("name,start", [("mesh118_T24", 0), ("mesh118_T24", 1), ("mesh14_tight_limits", 0),
-                                        ("cfg2", 0), ("mesh118_T24", 2), ("cfg2", 2), ("cfg4", 2)])
+                                        ("cfg2", 0), ("mesh118_T24", 2), ("cfg2", 2), ("cfg4", 0), ("cfg4", 2)])
 def test_step_graphs_match_kernel_by_kernel(name, start):
     """ucac_step's graphs run the fused iteration (two launches: the previous
     iteration's row finish with this iteration's unit side and lines, then the bus
