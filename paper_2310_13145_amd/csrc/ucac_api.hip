@@ -14,6 +14,7 @@
 
 #include "../../include/ucac.h"
 #include "ucac_launch.hpp"
+#include "ucac_solve_rule.hpp"
 
 using namespace ucac;
 
@@ -934,14 +935,12 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
     HIP_OR(h, launch_iterations(h, k));
     rc = read_status(h);
     if (rc) return rc;
-    // The tolerance is examined before the non-finite flag: a chunk that reached the
-    // tolerance and went non-finite only after it is replayed up to the stopping
-    // iteration, so the iterations after it never count.
+    // the tolerance before the non-finite flag (ucac_solve_rule.hpp)
     const int conv_iter = h->h_ctl->conv_iter;
-    if (conv_iter > 0) {
-      const int j = conv_iter - launched;  // the chunk's iteration at the tolerance, from 1
+    const ChunkAction act = chunk_action(conv_iter, h->h_ctl->bad, launched);
+    if (act.next == CHUNK_REPLAY) {
       HIP_OR(h, snapshot(true));
-      HIP_OR(h, launch_iterations(h, j - 1));
+      HIP_OR(h, launch_iterations(h, act.replay));
       h->h_ctl->stop_at_tol = 1;  // pinned staging
       HIP_OR(h, hipMemcpyAsync(&h->d_ctl->stop_at_tol, &h->h_ctl->stop_at_tol, sizeof(int), hipMemcpyHostToDevice,
                                h->stream));
@@ -956,7 +955,7 @@ int ucac_solve(ucac_handle* h, double tol, int32_t max_iters, int32_t* iters_don
       done = true;
       break;
     }
-    if (h->h_ctl->bad) break;
+    if (act.next == CHUNK_NONFINITE) break;
     launched += k;
   }
   rc = read_status(h);
