@@ -17,6 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libucac.so")
+# iterations per chunk of ucac_solve (SOLVE_CHUNK in csrc/ucac_api.hip): the solve runs
+# chunks from a snapshot and replays the one that reaches the tolerance
+SOLVE_CHUNK = 64
 
 UCAC_OK, UCAC_NOT_CONVERGED = 0, 1
 UCAC_E_INVAL, UCAC_E_NOMEM, UCAC_E_DEVICE, UCAC_E_STATE, UCAC_E_NUMERIC = -1, -2, -3, -4, -5

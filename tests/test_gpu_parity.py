@@ -181,7 +181,7 @@ def test_solve_stops_mid_chunk_without_trace():
     a = ucac.Solver(inst)
     a.branch_counters(reset=True)
     rc, n = a.solve(1e-2, 5000)
-    assert rc == 0 and n % 32 != 0  # stopped inside a chunk
+    assert rc == 0 and n % ucac.SOLVE_CHUNK != 0  # stopped inside a chunk
     ca = a.branch_counters()
     b = ucac.Solver(inst)
     b.branch_counters(reset=True)
@@ -199,19 +199,20 @@ def test_solve_stops_mid_chunk_without_trace():
 @pytest.mark.parametrize("edge", [1, 0])
 def test_solve_stops_at_chunk_edges(edge):
     """A solve whose tolerance is first met at the first (edge = 1) or the last
-    (edge = 0) iteration of one of its 32-iteration chunks: the tolerance is chosen
+    (edge = 0) iteration of one of its chunks (ucac.SOLVE_CHUNK iterations): the tolerance is chosen
     from a stepped run's residuals as a strict running minimum at such an iteration.
     The solve stops exactly there, and its iterate is that of stepping as far."""
     inst = synth.config_instance(1)
     a = ucac.Solver(inst)
     worst = []
-    for _ in range(700):
+    C = ucac.SOLVE_CHUNK
+    for _ in range(1700):  # (at 64 per chunk the first such minima fall after 1,500 iterations)
         a.step(1)
         rp, rd, _, _ = a.residuals()
         worst.append(max(rp, rd))
     worst = np.array(worst)
-    cand = [n for n in range(33, len(worst) + 1)
-            if n % 32 == edge and worst[n - 1] < worst[:n - 1].min()]
+    cand = [n for n in range(C + 1, len(worst) + 1)
+            if n % C == edge and worst[n - 1] < worst[:n - 1].min()]
     assert cand, "no running minimum at a chunk edge"
     n = cand[-1]
     print(f"[parity] chunk-edge solve stops at iteration {n} (tol {worst[n - 1]:.6e})", flush=True)

@@ -41,7 +41,7 @@ def test_chunk_rule(tmp_path):
         (40, 1, 32): (REPLAY, 7),    # tolerance at the chunk's 8th iteration, non-finite later: replay, no error
         (40, 0, 32): (REPLAY, 7),
         (33, 1, 32): (REPLAY, 0),    # at the chunk's first iteration: no step-mode iteration before it
-        (64, 0, 32): (REPLAY, 31),   # at its last (chunks of 32)
+        (64, 0, 32): (REPLAY, 31),   # at its last (a chunk of 32)
         (-1, 1, 32): (NONFINITE, 0),
         (-1, 0, 0): (CONTINUE, 0),
         (1, 0, 0): (REPLAY, 0),
