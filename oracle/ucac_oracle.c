@@ -382,7 +382,9 @@ static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol
   double g[4], H[4][4];
   for (int i = 0; i < 4; ++i) x[i] = clampd(x[i], b->lo[i], b->hi[i]);
   double F = branch_eval(b, x, g, H);
-  double delta = 1.0;
+  /* initial radius: the half-width of the per-unit voltage box, the scale on which the
+   * voltages move (the paper leaves the radius to the solver it cites) */
+  double delta = 0.1;
   int it;
   int cg_its = 0;
   for (it = 0; it < max_iter; ++it) {

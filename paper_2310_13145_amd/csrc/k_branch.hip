@@ -375,7 +375,10 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
 #pragma unroll
   for (int i = 0; i < 4; ++i) xe[i] = x[i];
   double F = 0.0, pred = 0.0, snorm = 0.0;
-  double delta = 1.0;
+  // initial radius 0.1: the half-width of the per-unit voltage box.  From the flat start
+  // a radius of 1 let the first step carry the voltages to their bound, and the slowest
+  // lanes then spent three or four iterations there before the quadratic phase.
+  double delta = 0.1;
   const double inv_rva = 1.0 / L.rva;
   bool trial = false;
   conv = false;
