@@ -412,7 +412,7 @@ static int branch_solve(const branch_pb *b, double *x, int max_iter, double gtol
     double ratio = pred > 0.0 ? (pred <= 1e-12 * fabs(F) ? 1.0 : (F - Ft) / pred) : -1.0;
     double snorm = sqrt(dot4(s, s));
     if (ratio < 0.25) delta = 0.25 * snorm;
-    else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
+    else if (ratio > 0.75 && snorm >= 0.99 * delta) delta = fmin(4.0 * delta, 10.0);  /* TRON: up to 4x */
     if (ratio >= 1e-4) {
       for (int i = 0; i < 4; ++i) x[i] = xt[i];
       F = branch_eval(b, x, g, H);

@@ -395,7 +395,7 @@ __device__ inline int newton(const Line& L, const double (&lo)[4], const double 
       const bool gt_3quarter = pos && (noise || ared > 0.75 * pred);
       accept = pos && (noise || ared >= 1e-4 * pred);
       if (lt_quarter) delta = 0.25 * snorm;
-      else if (gt_3quarter && snorm >= 0.99 * delta) delta = fmin(2.0 * delta, 10.0);
+      else if (gt_3quarter && snorm >= 0.99 * delta) delta = fmin(4.0 * delta, 10.0);
       trial = false;
     }
     if (accept) {
