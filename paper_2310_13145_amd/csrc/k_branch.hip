@@ -748,15 +748,17 @@ k_front(Net n, State s, Par p, int nb_units, int gpb, int fin_units) {
 }
 
 // The first launch of the fused iteration (two launches per iteration; the second,
-// k_bus_fused, solves the bus QP and runs this launch's control step of the iteration
-// before).  With FUSE_PRO every block first finishes the previous iteration's rows
-// it owns: a line block the line ends of its own (line, t) items, lane for lane the
-// items of its Newton solves (bus_post_body); a unit block its generators' rows G1,
-// G2, C1-C6 and U1-U3, with their relaxed commitments committed (unit_rows_body).
-// With FUSE_WORK it then runs this iteration's work on them.  A line lane reads, of
-// what the finish writes, only its own item's rows and duplicates, which it wrote
-// itself; a unit block synchronises between the two parts.  A graph's first launch
-// runs the work alone, its last the finish alone.
+// k_bus_fused, solves the bus QP and runs the control step of the iteration before).
+// With FUSE_PRO every block first finishes the previous iteration's rows it owns: a
+// line block the line ends of its own (line, t) items, each lane the item of its own
+// Newton solve, whose targets it then takes from the finish's registers (branch_body
+// with FIN); a unit block its generators' rows G1, G2, C1-C6 and U1-U3, with their
+// relaxed commitments committed (unit_rows_body).  With FUSE_WORK it then runs this
+// iteration's work.  A line lane reads, of what the finish writes, only its own
+// item's rows and duplicates, which it wrote itself; a unit block synchronises between
+// the two parts.  A graph's first launch runs the work alone, its last the finish
+// alone (bus_post_body).  The learned start's instantiation has only the
+// finish-and-work path: its lanes evaluate the network between the finish and Newton.
 template <int START, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2)))
 k_front_fused(Net n, State s, Par p, int nb_units, int gpb, int mode) {
