@@ -50,6 +50,9 @@ FLOP_LANE = 94       # per solve: targets from duplicates/multipliers, start, fi
 # The profiled (kernel-by-kernel) pass starts from the iterate after PROF_FROM iterations and
 # times PROF_ITERS iterations, whatever --steps and --warmup are.
 PROF_FROM = 200
+# Residual balancing of the time_to_tol section: a decision after every ADAPT_EVERY-th
+# iteration, with the library's default factors (mu = 3, tau = 1.5)
+ADAPT_EVERY = 20
 PROF_ITERS = 100
 
 # Algorithmic HBM bytes per item, counted from the kernels' loads and stores (8 B per
@@ -230,11 +233,11 @@ def cpu_baseline(inst, seconds, state0=None):
 def time_to_tol(ucac, torch, inst, args):
     """Solve from the cold start to r_p, r_d <= tol with the flat and the previous-iterate
     Newton start, each with fixed penalties and with residual balancing of the penalty
-    classes (a decision after every 50th iteration); the device records the first
+    classes (a decision after every 20th iteration); the device records the first
     iteration under 1e-2, 1e-3 and 1e-4."""
     res = {}
-    for label, ws, adapt in (("plain", 0, 0), ("prev_iterate", 1, 0), ("plain_balanced", 0, 50),
-                             ("prev_iterate_balanced", 1, 50)):
+    for label, ws, adapt in (("plain", 0, 0), ("prev_iterate", 1, 0), ("plain_balanced", 0, ADAPT_EVERY),
+                             ("prev_iterate_balanced", 1, ADAPT_EVERY)):
         s = ucac.Solver(inst, warm_start=ws, adapt_every=adapt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -100,9 +100,9 @@ typedef struct {
    * (rounding noise).  The penalties in force are part of the iterate
    * (ucac_get_state); the multipliers are stored unscaled, so they stay valid.  With
    * it on, every iteration runs its control step as a kernel of its own. */
-  int32_t adapt_every; /* [0] */
-  double adapt_mu;     /* [10] */
-  double adapt_tau;    /* [2] */
+  int32_t adapt_every; /* [0]; 20 suits the benchmark meshes */
+  double adapt_mu;     /* [3] */
+  double adapt_tau;    /* [1.5] */
   int32_t adapt_max;   /* [20] */
   double adapt_span;   /* [100] */
 } ucac_params;

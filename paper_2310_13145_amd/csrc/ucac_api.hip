@@ -732,7 +732,7 @@ void ucac_params_default(ucac_params* p) {
   p->newton_max_iter = 50; p->newton_gtol = 1e-12;
   p->max_inner = 1000; p->eps_in0 = 1e-2; p->tol = 1e-4;
   p->warm_start = 0; p->device = 0;
-  p->adapt_every = 0; p->adapt_mu = 10.0; p->adapt_tau = 2.0; p->adapt_max = 20; p->adapt_span = 100.0;
+  p->adapt_every = 0; p->adapt_mu = 3.0; p->adapt_tau = 1.5; p->adapt_max = 20; p->adapt_span = 100.0;
 }
 
 int ucac_create(const ucac_network* net, const ucac_params* params, ucac_handle** out) {

@@ -122,8 +122,8 @@ def test_decisions_follow_the_rule():
 
 
 def test_rounding_level_class_keeps_its_penalty():
-    """The 118-bus workload with the default settings (a decision after every 50th
-    iteration): once the commitments equal their binary duplicates, the commitment
+    """The 118-bus workload with mu = 10, tau = 2 and a decision after every 50th
+    iteration: once the commitments equal their binary duplicates, the commitment
     rows' residuals are rounding noise, and that class keeps its penalty."""
     hit = _check_decisions(synth.config_instance(1), 10.0, 2.0, 50, 450)
     assert ("uc", "noise") in hit, hit
