@@ -254,6 +254,23 @@ def test_edge_cases():
     compare(g.get_state(), o.get_state(), single, 1e-8, "single_bus")
 
 
+@pytest.mark.parametrize("T", [4, 1])
+def test_no_units_matches_oracle(T):
+    """A network without generators (the unit side, the generator rows and their
+    residual slots are all empty; the bus QP balances the loads with line flows
+    alone): 60 iterations of the step graphs against the oracle, then 5 iterations
+    kernel by kernel."""
+    inst = synth.small_instance(9, 12, 0, T, seed=3 + T)
+    print(f"[parity] no units, T {T}", flush=True)
+    g, o = pair(inst)
+    g.step(60)
+    o.step(60)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, f"no units T{T}")
+    g.kernel_times(5)
+    o.step(5)
+    compare(g.get_state(), o.get_state(), inst, 1e-8, f"no units T{T}, kernel by kernel")
+
+
 @pytest.mark.parametrize("T", [150, 400])
 def test_long_horizon_matches_oracle(T):
     """Horizons whose unit-side DP tables no longer fit 16 units per 256-thread block
