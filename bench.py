@@ -445,21 +445,25 @@ def main():
     solver = ucac.Solver(inst)
     solver.step(args.warmup)
     state0 = solver.get_state()
+    solver.branch_counters(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
+    newton_plain = solver.branch_counters(reset=True)["newton"] / (args.steps * T * L)
 
     # the same timed region with the previous-iterate Newton start (warm start)
     warm = ucac.Solver(inst, warm_start=1)
     warm.step(args.warmup)
+    warm.branch_counters(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     warm.step(args.steps)
     torch.cuda.synchronize()
     dt_warm = time.perf_counter() - t0
+    newton_warm = warm.branch_counters(reset=True)["newton"] / (args.steps * T * L)
     warm.close()
 
     # profiled pass, independent of --steps/--warmup: from the iterate after
@@ -500,7 +504,8 @@ def main():
         "config": {"workload": name, "n_bus": N, "n_line": L, "n_gen": G, "T": T,
                    "branch_solves_per_step": lanes, "newton_start": "flat (plain method)"},
         "roofline": roof,
-        "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps},
+        "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps,
+                                    "newton_per_solve": newton_warm, "newton_per_solve_flat": newton_plain},
         "kernels_ms": ktimes,
         "profiled_ms_per_step": prof_ms_per_step,
         "hbm": hbm,
