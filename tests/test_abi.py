@@ -116,3 +116,14 @@ def test_dp_batch_validation(lib):
     assert lib.ucac_dp_batch(10, 24, *([None] * 8), 64, None) == ucac.UCAC_E_INVAL  # null pointers
     assert "null" in ucac.ucac_last_error(None)
     assert lib.ucac_dp_batch(0, 24, *([None] * 8), 64, None) == ucac.UCAC_OK  # nothing to do
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises at once: there is no CPU path
+    to fall back to, and creating a solver fails rather than running anything else."""
+    monkeypatch.setattr(ucac, "_lib", None)
+    monkeypatch.setattr(ucac, "LIB_PATH", str(tmp_path / "libucac.so"))
+    with pytest.raises(ImportError, match="missing"):
+        ucac.lib()
+    with pytest.raises(ImportError, match="missing"):
+        ucac.Solver(synth.small_instance(9, 12, 3, 2, seed=1))
