@@ -131,7 +131,7 @@ int ucac_step(ucac_handle* h, int32_t n_iters);
 /* Iterate until r_p <= tol and r_d <= tol (UCAC_OK) or until max_iters inner
  * iterations (UCAC_NOT_CONVERGED).  The stopping iteration is decided on the
  * device, so the result does not depend on how often the host polls: the call runs
- * chunks of 32 iterations from a snapshot, and a chunk that reaches the tolerance is
+ * chunks of 64 iterations from a snapshot, and a chunk that reaches the tolerance is
  * replayed from its snapshot to stop exactly there (state, multipliers, milestones
  * and work counters as if the iterations after it never ran).  Allocates the
  * snapshot (the state's size) on its first call.
