@@ -76,7 +76,7 @@ BYTES_BUS_POST = 8 * 64     # per (line, t), both ends: flows, targets, bus resu
 # mesh2000_T24 bench command), each scaled by the ratio of true to counted bytes of a
 # plain copy kernel of known size.  They describe the kernel source they were taken
 # on (hash below) and are reported as null once that source has changed.
-BRANCH_COUNTERS = {"source_sha256": "c783356a2e955d6005420aa38a892ec75fbae69528a81c48120f2e86fd7dce2c",
+BRANCH_COUNTERS = {"source_sha256": "791c865a1f07ddf19cd8f420765b8a7baef161b51d81ffe40a8ce08994a98044",
                    "fetch_kib": 8049.0, "write_kib": 11196.4, "fetch_scale": 2.0, "write_scale": 1.0}
 # the line kernel's translation unit and every header it includes
 BRANCH_SOURCES = ('k_branch.hip', 'ucac_mlp.hpp', 'ucac_dev.hpp', 'ucac_launch.hpp', 'ucac_units.hpp', 'ucac_ctl.hpp',
@@ -110,7 +110,8 @@ def line_roofline(solver, inst, from_iter):
     solver.branch_counters(reset=True)
     ktimes = solver.kernel_times(PROF_ITERS)
     cnt = solver.branch_counters(reset=True)
-    branch_dispatch_ms = ktimes.pop("branch_dispatch")
+    dispatch = {k: ktimes.pop(f"{k}_dispatch") for k in list(ktimes) if not k.endswith("_dispatch")}
+    branch_dispatch_ms = dispatch["branch"]
     lanes = inst["T"] * inst["n_line"]
     # the kernel evaluates value, gradient and Hessian at the start and at every trial
     # point; the method needs the full evaluation at the start and at accepted points and
@@ -129,7 +130,7 @@ def line_roofline(solver, inst, from_iter):
             "projected_searches_per_launch": cnt["searches"] / PROF_ITERS,
             "profiled_iterations": f"{PROF_ITERS} kernel-by-kernel iterations from the iterate after "
                                    f"{from_iter}, after one untimed iteration"}
-    return roof, ktimes
+    return roof, ktimes, dispatch
 
 
 def parse():
@@ -473,16 +474,19 @@ def main():
     # taken from its dispatch timestamps, what a kernel trace of the same run reports
     solver.set_state(state0)
     solver.step(max(0, PROF_FROM - args.warmup))
-    roof, ktimes = line_roofline(solver, inst, max(PROF_FROM, args.warmup))
+    roof, ktimes, dispatch = line_roofline(solver, inst, max(PROF_FROM, args.warmup))
     roof["traffic"] = branch_traffic()
-    prof_ms_per_step = sum(ktimes.values())
+    prof_ms_per_step = sum(dispatch.values())
     lanes = T * L
     bytes_bus = 2 * L * T * BYTES_BUS_END + N * T * BYTES_BUS_BUS + G * T * BYTES_BUS_GEN
+    # algorithmic bytes over each kernel's dispatch-timestamp mean (the event pairs
+    # around a kernel also count the dispatch latency; kept as ms_between_events)
     hbm = {
-        "post": {"bytes": lanes * BYTES_BUS_POST + G * T * BYTES_GEN_DUAL, "ms": ktimes["post"]},
-        "units": {"bytes": G * T * BYTES_UNITS, "ms": ktimes["units"]},
-        "bus": {"bytes": bytes_bus, "ms": ktimes["bus"]},
-        "branch": {"bytes": lanes * BYTES_BRANCH, "ms": ktimes["branch"]},
+        "post": {"bytes": lanes * BYTES_BUS_POST + G * T * BYTES_GEN_DUAL, "ms": dispatch["post"],
+                 "ms_between_events": ktimes["post"]},
+        "units": {"bytes": G * T * BYTES_UNITS, "ms": dispatch["units"], "ms_between_events": ktimes["units"]},
+        "bus": {"bytes": bytes_bus, "ms": dispatch["bus"], "ms_between_events": ktimes["bus"]},
+        "branch": {"bytes": lanes * BYTES_BRANCH, "ms": dispatch["branch"], "ms_between_events": ktimes["branch"]},
     }
     for v in hbm.values():
         v["GB_s"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
@@ -507,6 +511,7 @@ def main():
         "warm_start_prev_iterate": {"value": args.steps / dt_warm, "ms_per_step": 1e3 * dt_warm / args.steps,
                                     "newton_per_solve": newton_warm, "newton_per_solve_flat": newton_plain},
         "kernels_ms": ktimes,
+        "kernels_dispatch_ms": dispatch,
         "profiled_ms_per_step": prof_ms_per_step,
         "hbm": hbm,
     }
@@ -518,7 +523,7 @@ def main():
         big = synth.config_instance(4)
         s4 = ucac.Solver(big)
         s4.step(PROF_FROM)
-        out["roofline_" + synth.CONFIGS[4]["name"]], _ = line_roofline(s4, big, PROF_FROM)
+        out["roofline_" + synth.CONFIGS[4]["name"]], _, _ = line_roofline(s4, big, PROF_FROM)
         s4.close()
 
     if not args.no_solve:

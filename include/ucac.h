@@ -205,9 +205,10 @@ int ucac_get_line_starts(const ucac_handle* h, float* x0);
  * stream before and after it; avg_ms[k] (n_slots >= UCAC_N_KERNELS) receives the
  * mean device time of kernel k per iteration.  Those event pairs also count the
  * latency between an event record and the next dispatch.  With n_slots >
- * UCAC_N_KERNELS, avg_ms[UCAC_N_KERNELS] also receives the line kernel's mean
- * duration taken from its own dispatch's begin and end timestamps (the figure
- * a kernel trace reports; the learned start's network kernel is not in it).
+ * UCAC_N_KERNELS, avg_ms[UCAC_N_KERNELS + k] (for UCAC_N_KERNELS + k < n_slots)
+ * also receives kernel k's mean duration taken from its own dispatch's begin and
+ * end timestamps (the figure a kernel trace reports; the line kernel's does not
+ * include the learned start's network kernel; 0 for a kernel without work).
  * Synchronous. */
 int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots);
 

@@ -18,6 +18,7 @@
 //            order); then one lane per (g, t) for z and y of rows C1..C6 and
 //            U1..U3, which also commits the new relaxed commitments.
 // Each kernel stores its blocks' residual maxima into per-block slots.
+#include <hip/hip_ext.h>
 #include "ucac_launch.hpp"
 #include "ucac_rows.hpp"
 #include "ucac_ctl.hpp"
@@ -319,6 +320,19 @@ void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st) {
   const int nb = post_blocks(n);
   if (nb == 0) return;
   hipLaunchKernelGGL(k_post, dim3(nb), dim3(BLOCK), 0, st, n, s, p);
+}
+
+bool launch_bus_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (n.T * n.N == 0) return false;
+  hipExtLaunchKernelGGL(k_bus, dim3(bus_blocks(n)), dim3(BLOCK), 0, st, e0, e1, 0u, n, s, p);
+  return true;
+}
+
+bool launch_post_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const int nb = post_blocks(n);
+  if (nb == 0) return false;
+  hipExtLaunchKernelGGL(k_post, dim3(nb), dim3(BLOCK), 0, st, e0, e1, 0u, n, s, p);
+  return true;
 }
 
 }  // namespace ucac

@@ -858,8 +858,9 @@ void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t
   launch_branch_impl(n, s, p, st, block, nullptr, nullptr);
 }
 
-void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+bool launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   launch_branch_impl(n, s, p, st, 256, e0, e1);
+  return n.T * n.L > 0;
 }
 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_branch_block(n, s, p, st, 256); }

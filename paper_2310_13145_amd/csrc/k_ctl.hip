@@ -2,6 +2,7 @@
 // the step:outer multiplier update applied to every row for a call that ends with
 // it pending (within an iteration the row owners apply it).
 #include "ucac_ctl.hpp"
+#include <hip/hip_ext.h>
 #include "ucac_launch.hpp"
 
 namespace ucac {
@@ -18,6 +19,11 @@ __global__ void __launch_bounds__(FIN_BLOCK) k_finalize_ranges(State s, Par p, S
 
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, n, s, p);
+}
+
+bool launch_finalize_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, st, e0, e1, 0u, n, s, p);
+  return true;
 }
 
 void launch_finalize_ranges(const State& s, const Par& p, const SlotRanges& R, hipStream_t st) {

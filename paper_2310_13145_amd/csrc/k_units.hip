@@ -2,6 +2,7 @@
 // the standalone batch of dynamic programs on given cost tables.
 //
 // This file is compiled with -ffp-contract=off.
+#include <hip/hip_ext.h>
 #include "ucac_launch.hpp"
 #include "ucac_units.hpp"
 
@@ -78,5 +79,13 @@ void launch_units_lanes(const Net& n, const State& s, const Par& p, hipStream_t 
 }
 
 void launch_units(const Net& n, const State& s, const Par& p, hipStream_t st) { launch_units_lanes(n, s, p, st, 16); }
+
+bool launch_units_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (n.G == 0 || n.T == 0) return false;
+  const int gpb = units_gpb(n.T, 16, 256);
+  hipExtLaunchKernelGGL(k_units, dim3(units_blocks(n, gpb)), dim3(UNIT_BLOCK), units_lds(n.T, gpb), st, e0, e1, 0u, n, s,
+                        p, gpb);
+  return true;
+}
 
 }  // namespace ucac

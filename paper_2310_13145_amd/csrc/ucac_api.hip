@@ -1129,27 +1129,38 @@ int ucac_get_line_starts(const ucac_handle* hc, float* x0) {
   return UCAC_OK;
 }
 
+// Kernel k of the kernel-by-kernel iteration launched with its own start and stop
+// events; false where it has no work (nothing launched).
+static bool launch_timed(ucac_handle* h, int k, hipEvent_t e0, hipEvent_t e1) {
+  static bool (*const fns[])(const Net&, const State&, const Par&, hipStream_t, hipEvent_t, hipEvent_t) = {
+      launch_units_timed, launch_branch_timed, launch_bus_timed, launch_post_timed, launch_finalize_timed};
+  return fns[k](h->net, h->st, h->kp, h->stream, e0, e1);
+}
+
 int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n_slots) {
   if (!h || !avg_ms || n_iters < 1 || n_slots < UCAC_N_KERNELS) return h ? fail(h, UCAC_E_INVAL, "bad arguments") : UCAC_E_INVAL;
   HIP_OR(h, hipSetDevice(h->par.device));
   int rc = set_ctl(h, 0, h->par.tol);
   if (rc) return rc;
   const int K = UCAC_N_KERNELS;
-  const bool dispatch = n_slots > K;
-  // K + 1 markers per iteration, then (dispatch timing) the line kernel's own pair
-  const int E = K + 1 + (dispatch ? 2 : 0);
+  // kernels 0 .. nd-1 also carry their own dispatch events (slots K + k)
+  const int nd = n_slots - K < K ? n_slots - K : K;
+  // K + 1 markers per iteration, then a pair per dispatch-timed kernel
+  const int E = K + 1 + 2 * nd;
   std::vector<hipEvent_t> ev((size_t)n_iters * E, nullptr);
   for (auto& e : ev) HIP_OR(h, hipEventCreate(&e));
   hipError_t err = hipSuccess;
   const char* where = "";
+  static const char* names[] = {"units", "branch", "bus", "post", "finalize"};
+  bool launched[UCAC_N_KERNELS] = {};
   for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
     hipEvent_t* e = &ev[(size_t)it * E];
     err = hipEventRecord(e[0], h->stream);
     for (int k = 0; k < K && err == hipSuccess; ++k) {
-      if (k == K_BRANCH && dispatch) {
-        launch_branch_timed(h->net, h->st, h->kp, h->stream, e[K + 1], e[K + 2]);
+      if (k < nd) {
+        launched[k] = launch_timed(h, k, e[K + 1 + 2 * k], e[K + 2 + 2 * k]);
         err = hipGetLastError();
-        if (err != hipSuccess) where = "branch";
+        if (err != hipSuccess) where = names[k];
       } else {
         err = launch_one(h, k, h->stream, &where);
       }
@@ -1157,7 +1168,7 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
     }
   }
   if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
-  for (int k = 0; k < n_slots && k <= K; ++k) avg_ms[k] = 0.0;
+  for (int k = 0; k < n_slots && k < K + nd; ++k) avg_ms[k] = 0.0;
   for (int it = 0; it < n_iters && err == hipSuccess; ++it) {
     const hipEvent_t* e = &ev[(size_t)it * E];
     for (int k = 0; k < K && err == hipSuccess; ++k) {
@@ -1165,11 +1176,12 @@ int ucac_kernel_times(ucac_handle* h, int32_t n_iters, double* avg_ms, int32_t n
       err = hipEventElapsedTime(&ms, e[k], e[k + 1]);
       avg_ms[k] += ms / n_iters;
     }
-    // an empty instance launches no line kernel and leaves the pair unrecorded
-    if (dispatch && err == hipSuccess && h->T * h->L > 0) {
+    // a kernel without work launches nothing and leaves its pair unrecorded
+    for (int k = 0; k < nd && err == hipSuccess; ++k) {
+      if (!launched[k]) continue;
       float ms = 0.0f;
-      err = hipEventElapsedTime(&ms, e[K + 1], e[K + 2]);
-      avg_ms[K] += ms / n_iters;
+      err = hipEventElapsedTime(&ms, e[K + 1 + 2 * k], e[K + 2 + 2 * k]);
+      avg_ms[K + k] += ms / n_iters;
     }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);

@@ -10,7 +10,15 @@ void launch_units_lanes(const Net& n, const State& s, const Par& p, hipStream_t 
 void launch_branch(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_branch_block(const Net& n, const State& s, const Par& p, hipStream_t st, int block);
 // The line kernel at 256-lane blocks, timed by the dispatch's own start/stop events.
-void launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+// Timed launches of the kernel-by-kernel iteration's kernels: the launch carries its
+// own start and stop events (the dispatch's begin and end timestamps); false where the
+// kernel has no work and nothing was launched (the events stay unrecorded).  The line
+// kernel's pair does not cover the learned start's network kernel launched before it.
+bool launch_units_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+bool launch_branch_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+bool launch_bus_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+bool launch_post_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+bool launch_finalize_timed(const Net& n, const State& s, const Par& p, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 void launch_bus(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_post(const Net& n, const State& s, const Par& p, hipStream_t st);
 void launch_finalize(const Net& n, const State& s, const Par& p, hipStream_t st);  // slots: standard_ranges(s, s.red_u)

@@ -290,12 +290,14 @@ KERNELS = ("units", "branch", "bus", "post", "finalize")
 
 
 def ucac_kernel_times(h, n_iters):
-    """n_iters iterations launched kernel by kernel with HIP events; mean ms per kernel,
-    plus "branch_dispatch": the line kernel's mean from its dispatch's own timestamps."""
-    out = np.zeros(len(KERNELS) + 1)
+    """n_iters iterations launched kernel by kernel with HIP events; mean ms per kernel
+    between event records, and "<kernel>_dispatch": its mean from its dispatch's own
+    begin and end timestamps."""
+    K = len(KERNELS)
+    out = np.zeros(2 * K)
     _check(lib().ucac_kernel_times(h, int(n_iters), _ptr(out), len(out)), h)
-    d = dict(zip(KERNELS, out[:len(KERNELS)].tolist()))
-    d["branch_dispatch"] = float(out[len(KERNELS)])
+    d = dict(zip(KERNELS, out[:K].tolist()))
+    d.update({f"{k}_dispatch": float(out[K + i]) for i, k in enumerate(KERNELS)})
     return d
 
 
