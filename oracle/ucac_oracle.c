@@ -31,6 +31,12 @@
  * Parity pins: see tests/test_oracle_*.py (brute-force DP, block optimality
  * against generic solvers, finite differences, closed forms, AC power-flow
  * residuals at convergence).
+ *
+ * Parity unpinned: which local minimiser and which commitments the non-convex
+ * iteration reaches on the 118- and 2000-bus workloads.  The paper prints no worked
+ * example and its Table 1 needs data that is not available, so those trajectories
+ * are checked only against this oracle (their blocks and stopping point are pinned
+ * as above).
  */
 #include <math.h>
 #include <omp.h>
