@@ -212,7 +212,8 @@ __device__ __forceinline__ void bus_body_t(const Net& n, const State& s, const P
   const double v[4] = {rp, rin, rd, zinf};
   const int which[4] = {ACC_RP, ACC_RIN, ACC_RD, ACC_ZINF};
   block_max_store<4>(v, which, s.red + (size_t)(s.red_bus + blk) * NACC);
-  if (ROWS && p.adapt_every > 0) {
+  if (p.adapt_every > 0) {
+    // (without the rows G1, G2 their class maxima come from the unit blocks' finish)
     const double vc[5] = {rin_pq, y_pq, dx_va, dx_pq, dx_pb};
     const int wc[5] = {CS_RIN + CL_PQ, CS_Y + CL_PQ, CS_DX + CL_VA, CS_DX + CL_PQ, CS_DX + CL_CPL};
     block_max_store<5, NCS>(vc, wc, s.redc + (size_t)(s.red_bus + blk) * NCS);

@@ -82,6 +82,10 @@ struct ucac_handle {
   double* h_sc = nullptr;    // pinned staging of the scalars
   GraphSet graphs;        // step mode: GRAPH_SIZES[j] iterations, control steps inside the next front launch
   GraphSet graphs_solve;  // solve mode: GRAPH_SIZES[j] iterations, each with its own control-step kernel
+  // step mode with residual balancing: one period of adapt_every fused iterations
+  // (the last one's control step decides), or null
+  hipGraph_t g_period = nullptr;
+  hipGraphExec_t x_period = nullptr;
   hipEvent_t ev_poll = nullptr;
   HostGen hg;
   int cus = 0;               // compute units of the device
@@ -590,9 +594,10 @@ hipError_t enqueue_step_iteration(ucac_handle* h, hipStream_t st, int r, int siz
 // thus runs beside the bus solve of r, which writes the other bus copy.  Every
 // iterate is the kernel-by-kernel iteration's bit for bit: the same item arithmetic,
 // each row updated once per iteration after the values it reads, and maxima whose
-// grouping does not change them.  Not with residual balancing (its control step
-// changes penalties the next bus solve reads).  With the learned start the line lanes
-// evaluate the network between the finish and the Newton solve.
+// grouping does not change them.  With residual balancing an iteration whose control
+// step decides must end a graph (launch_balanced): that step changes penalties the
+// next bus solve reads.  With the learned start the line lanes evaluate the network
+// between the finish and the Newton solve.
 hipError_t enqueue_fused_iteration(ucac_handle* h, hipStream_t st, int r, int size, const char** where) {
   const State& s0 = h->st;
   const int ucopy[2] = {s0.red_units, s0.red_n};
@@ -628,19 +633,15 @@ bool front_queues(const ucac_handle* h) {
   return 4L * (unit_blocks + line_blocks) > 8L * h->cus;
 }
 
-// The step graphs' form: fused, unless residual balancing is on (its calls run the
-// solve-mode graphs) or the learned start's network would hold back a launch of
-// several rounds of wavefronts; then the pipelined form.  Inside the fused launch
-// the network saves a kernel and the reads of its inputs, which pays where the whole
-// launch is resident at once (its time is the slowest lane's latency); its registers
-// there lower what the line kernel's lanes may hold, which costs more where they
-// queue for the CUs, and there the network kernel runs at its own occupancy (measured
-// at 76,800 and 624,000 line solves: 0.96x and 0.92x of the plain iteration in the
-// fused launch, 0.92x and 0.99x as a kernel of its own).
-bool use_fused(const ucac_handle* h) {
-  if (h->kp.adapt_every > 0) return false;
-  return h->kp.warm_start != 2 || !front_queues(h);
-}
+// The step graphs' form: fused, unless the learned start's network would hold back a
+// launch of several rounds of wavefronts; then the pipelined form.  Inside the fused
+// launch the network saves a kernel and the reads of its inputs, which pays where the
+// whole launch is resident at once (its time is the slowest lane's latency); its
+// registers there lower what the line kernel's lanes may hold, which costs more where
+// they queue for the CUs, and there the network kernel runs at its own occupancy
+// (measured at 76,800 and 624,000 line solves: 0.96x and 0.92x of the plain iteration
+// in the fused launch, 0.92x and 0.99x as a kernel of its own).
+bool use_fused(const ucac_handle* h) { return h->kp.warm_start != 2 || !front_queues(h); }
 
 // One kernel of the iteration by index (the order of enqueue_iteration).
 hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where, const State* sv = nullptr) {
@@ -653,9 +654,32 @@ hipError_t launch_one(ucac_handle* h, int k, hipStream_t st, const char** where,
   return e;
 }
 
+void clear_period_graph(ucac_handle* h) {
+  if (h->x_period) (void)hipGraphExecDestroy(h->x_period);
+  if (h->g_period) (void)hipGraphDestroy(h->g_period);
+  h->x_period = nullptr;
+  h->g_period = nullptr;
+}
+
+// The longest balancing period captured as one graph; longer periods are split.
+constexpr int MAX_PERIOD_GRAPH = 256;
+
 int build_graph(ucac_handle* h) {
   h->graphs.clear();
   h->graphs_solve.clear();
+  clear_period_graph(h);
+  const int K = h->kp.adapt_every;
+  if (K > 1 && K <= MAX_PERIOD_GRAPH && use_fused(h)) {
+    (void)hipGetLastError();
+    HIP_OR(h, hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
+    const char* where = "";
+    hipError_t le = hipSuccess;
+    for (int r = 0; r < K && le == hipSuccess; ++r) le = enqueue_fused_iteration(h, h->own, r, K, &where);
+    const hipError_t ce = hipStreamEndCapture(h->own, &h->g_period);
+    if (le != hipSuccess) return fail(h, UCAC_E_DEVICE, "launch of kernel %s failed: %s", where, hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(h, UCAC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+    HIP_OR(h, hipGraphInstantiate(&h->x_period, h->g_period, nullptr, nullptr, 0));
+  }
   for (int solve = 0; solve < 2; ++solve) {
     GraphSet& gs = solve ? h->graphs_solve : h->graphs;
     for (int j = 0; j < N_GRAPHS; ++j) {
@@ -678,13 +702,36 @@ int build_graph(ucac_handle* h) {
   return UCAC_OK;
 }
 
+// With residual balancing, a control step that decides (after every adapt_every-th
+// iteration) may change the penalties, which the next iteration's kernels read, so it
+// cannot run beside them.  In the fused step graphs only a graph's last iteration has
+// its control step after its own rows and before the next launch: the n iterations
+// are split at every deciding iteration (read the iterate's counter first), so that
+// each deciding iteration ends a graph.  The pipelined form runs its control step
+// beside the next front launch in every iteration: there the solve-mode graphs (a
+// control-step kernel after every iteration, here without stopping) are used instead.
+hipError_t launch_balanced(ucac_handle* h, int n) {
+  hipError_t e = hipMemcpyAsync(&h->h_sc[SC_ITER], h->st.sc + SC_ITER, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  const long K = h->kp.adapt_every;
+  long it = (long)h->h_sc[SC_ITER];
+  while (e == hipSuccess && n > 0) {
+    const long to_decision = K - it % K;
+    const int seg = (long)n < to_decision ? n : (int)to_decision;
+    // a whole period: its own graph where captured
+    e = seg == K && h->x_period ? hipGraphLaunch(h->x_period, h->stream) : h->graphs.launch(seg, h->stream);
+    it += seg;
+    n -= seg;
+  }
+  return e;
+}
+
 // Enqueue n iterations, largest graph first (solve mode: with a control-step kernel
 // after every iteration).
-// With residual balancing on, every iteration keeps its control-step kernel (the
-// solve-mode graphs, here without stopping): a control step may change the penalties,
-// which the next iteration's kernels read, so it cannot run beside them.
 hipError_t launch_iterations(ucac_handle* h, int n, bool solve = false) {
-  return (solve || h->kp.adapt_every > 0 ? h->graphs_solve : h->graphs).launch(n, h->stream);
+  if (solve) return h->graphs_solve.launch(n, h->stream);
+  if (h->kp.adapt_every > 0) return use_fused(h) ? launch_balanced(h, n) : h->graphs_solve.launch(n, h->stream);
+  return h->graphs.launch(n, h->stream);
 }
 
 // Write the host-owned control fields (never inside a captured graph).
@@ -1632,6 +1679,7 @@ void ucac_destroy(ucac_handle* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   h->graphs.clear();
   h->graphs_solve.clear();
+  clear_period_graph(h);
   if (h->ev_poll) (void)hipEventDestroy(h->ev_poll);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);

@@ -133,13 +133,14 @@ __device__ inline void cu_rows_item(const Net& n, const State& s, const Par& p, 
 // stored: a = p - pbar and q - qbar (the bus kernel's own update of these rows takes
 // the same values from its registers).
 __device__ inline void g12_rows_item(const State& s, const Par& p, const int TG, const int i, const double beta,
-                                     const LamUpd& lu, double& rp, double& rin, double& zinf) {
+                                     const LamUpd& lu, double& rp, double& rin, double& zinf, double& rin_pq,
+                                     double& y_pq) {
 #pragma clang fp contract(off)
   RowZY r1 = row_load(s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, i);
   RowZY r2 = row_load(s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, i);
   const double a1 = s.p[i] - s.pb[i], a2 = s.q[i] - s.qb[i];
-  row_update(r1, a1, p.rho_pq, beta, lu, rp, rin, zinf);
-  row_update(r2, a2, p.rho_pq, beta, lu, rp, rin, zinf);
+  row_update_c(r1, a1, p.rho_pq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
+  row_update_c(r2, a2, p.rho_pq, beta, lu, rp, rin, zinf, rin_pq, y_pq);
   row_store(r1, s.zG + RG_G1 * TG, s.yG + RG_G1 * TG, s.lG + RG_G1 * TG, i, lu);
   row_store(r2, s.zG + RG_G2 * TG, s.yG + RG_G2 * TG, s.lG + RG_G2 * TG, i, lu);
 }
@@ -241,8 +242,10 @@ __device__ __forceinline__ void bus_post_body(const Net& n, const State& s, cons
 // The previous iteration's generator rows, finished by the unit block that owns the
 // generators before its own work (the fused iteration): for each of the block's gpb
 // generators (the unit side's lane mapping) and every period, rows G1, G2 and then the
-// coupling and commitment rows; residual maxima to slot red_ugen + blk.  The caller
-// synchronises the block before the generators' update reads these rows.
+// coupling and commitment rows; residual maxima to slot red_ugen + blk, and with
+// residual balancing the rows' class maxima to the same slot of redc (what the bus
+// kernel and the generator-row kernel store for these rows in the four-launch form).
+// The caller synchronises the block before the generators' update reads these rows.
 template <int BS>
 __device__ __forceinline__ void unit_rows_body(const Net& n, const State& s, const Par& p0, const int blk, const int gpb) {
   if (s.ctl->halt) return;
@@ -251,19 +254,24 @@ __device__ __forceinline__ void unit_rows_body(const Net& n, const State& s, con
   const int gsub = threadIdx.x % gpb, tb = threadIdx.x / gpb;
   const int g = blk * gpb + gsub;
   double rp = 0.0, rin = 0.0, zinf = 0.0;
+  double rin_pq = 0.0, y_pq = 0.0, rin_c = 0.0, rin_u = 0.0, y_c = 0.0, y_u = 0.0;  // class maxima
   if (g < G) {
     const double beta = s.sc[SC_BETA];
     const LamUpd lu = lambda_pending(s, p);
-    double rin_c = 0.0, rin_u = 0.0, y_c = 0.0, y_u = 0.0;  // class maxima: unused here
     for (int t = tb; t < T; t += TPAR) {
       const int i = t * G + g;
-      g12_rows_item(s, p, TG, i, beta, lu, rp, rin, zinf);
+      g12_rows_item(s, p, TG, i, beta, lu, rp, rin, zinf, rin_pq, y_pq);
       cu_rows_item(n, s, p, t, g, i, beta, lu, rp, rin, zinf, rin_c, rin_u, y_c, y_u);
     }
   }
   const double v[3] = {rp, rin, zinf};
   const int which[3] = {ACC_RP, ACC_RIN, ACC_ZINF};
   block_max_store<3>(v, which, s.red + (size_t)(s.red_ugen + blk) * NACC);
+  if (p.adapt_every > 0) {
+    const double vc[6] = {rin_pq, y_pq, rin_c, rin_u, y_c, y_u};
+    const int wc[6] = {CS_RIN + CL_PQ, CS_Y + CL_PQ, CS_RIN + CL_CPL, CS_RIN + CL_UC, CS_Y + CL_CPL, CS_Y + CL_UC};
+    block_max_store<6, NCS>(vc, wc, s.redc + (size_t)(s.red_ugen + blk) * NCS);
+  }
 }
 
 }  // namespace ucac

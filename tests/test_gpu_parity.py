@@ -538,6 +538,34 @@ def test_residual_balancing_matches_oracle():
     assert min(S["nchg_pq"], S["nchg_va"], S["nchg_cpl"], S["nchg_uc"]) > 0
 
 
+@pytest.mark.parametrize("name,every", [("adapt14", 3), ("mesh118_T24", 20), ("cfg2", 20)])
+def test_residual_balancing_fused_steps_match_kernel_by_kernel(name, every):
+    """With residual balancing the step calls run the fused graphs, split so that every
+    iteration whose control step decides ends a graph: the iterates, penalties and
+    change counts equal the kernel-by-kernel iteration's bit for bit, across calls
+    that start and end between decisions, a state set mid-period, and graph sizes."""
+    inst = {"adapt14": _adapt_instance, "mesh118_T24": lambda: synth.config_instance(1),
+            "cfg2": lambda: synth.config_instance(2)}[name]()
+    over = dict(adapt_every=every, adapt_mu=1.5, adapt_max=1000, adapt_span=1e6)
+    print(f"[parity] balanced fused vs kernel-by-kernel {name} every {every}", flush=True)
+    a = ucac.Solver(inst, **over)
+    b = ucac.Solver(inst, **over)
+    done = 0
+    for n in (1, 5, 16, 70, 7):
+        a.step(n)
+        b.kernel_times(n)
+        done += n
+        np.testing.assert_array_equal(a.get_state(), b.get_state(), err_msg=f"after {done} iterations")
+    mid = a.get_state()
+    a.set_state(mid)
+    b.set_state(mid)
+    a.step(43)
+    b.kernel_times(43)
+    np.testing.assert_array_equal(a.get_state(), b.get_state(), err_msg="after a state set mid-period")
+    S = ucac.split_state(a.get_state(), *dims(inst))
+    assert S["nchg_pq"] + S["nchg_va"] + S["nchg_cpl"] + S["nchg_uc"] > 0
+
+
 def test_residual_balancing_solve_mesh118():
     """The 118-bus workload solved to 1e-4 with the default balancing factors and a
     decision after every 20th iteration (the benchmark's setting): the same stopping
