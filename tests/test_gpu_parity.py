@@ -538,18 +538,26 @@ def test_residual_balancing_matches_oracle():
     assert min(S["nchg_pq"], S["nchg_va"], S["nchg_cpl"], S["nchg_uc"]) > 0
 
 
-@pytest.mark.parametrize("name,every", [("adapt14", 3), ("mesh118_T24", 20), ("cfg2", 20)])
-def test_residual_balancing_fused_steps_match_kernel_by_kernel(name, every):
+@pytest.mark.parametrize("name,every,start", [("adapt14", 3, 0), ("mesh118_T24", 20, 0), ("cfg2", 20, 0),
+                                              ("mesh118_T24", 7, 1), ("mesh118_T24", 7, 2)])
+def test_residual_balancing_fused_steps_match_kernel_by_kernel(name, every, start):
     """With residual balancing the step calls run the fused graphs, split so that every
     iteration whose control step decides ends a graph: the iterates, penalties and
     change counts equal the kernel-by-kernel iteration's bit for bit, across calls
-    that start and end between decisions, a state set mid-period, and graph sizes."""
+    that start and end between decisions, a state set mid-period, and graph sizes; with
+    the flat, previous-iterate and learned (an untrained network) Newton starts."""
     inst = {"adapt14": _adapt_instance, "mesh118_T24": lambda: synth.config_instance(1),
             "cfg2": lambda: synth.config_instance(2)}[name]()
-    over = dict(adapt_every=every, adapt_mu=1.5, adapt_max=1000, adapt_span=1e6)
-    print(f"[parity] balanced fused vs kernel-by-kernel {name} every {every}", flush=True)
+    over = dict(adapt_every=every, adapt_mu=1.5, adapt_max=1000, adapt_span=1e6, warm_start=min(start, 1))
+    print(f"[parity] balanced fused vs kernel-by-kernel {name} every {every} start {start}", flush=True)
     a = ucac.Solver(inst, **over)
     b = ucac.Solver(inst, **over)
+    if start == 2:
+        net = ucac.WarmStartNet(seed=8)
+        w = net.get_weights()
+        net.close()
+        a.set_warmstart(w)
+        b.set_warmstart(w)
     done = 0
     for n in (1, 5, 16, 70, 7):
         a.step(n)
